@@ -1,0 +1,262 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself:
+  * closed-form separations (tests/golden), exact by geometry;
+  * exact rational decisions where the separation is a plain difference
+    (same meridian, the equator, across a pole);
+  * an independent 60-digit ``decimal`` evaluation for generic geometry;
+  * brute force over all pairs on small adversarial inputs (completeness of
+    the zone join);
+  * symmetries of the exact pair set (swap, RA rotation, reflections);
+  * the expected number of counterpart and chance pairs of the small patch
+    workload.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import hp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_form_separations.txt")
+
+
+def _golden():
+    rows = []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, kind, ra1, dec1, ra2, dec2, sep = line.split()
+        rows.append((name, kind, float(ra1), float(dec1), float(ra2), float(dec2), Fraction(sep)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden(), ids=lambda r: r[0])
+def test_closed_form_separations(row):
+    name, kind, ra1, dec1, ra2, dec2, sep = row
+    exact = float(sep)
+    # FP64 path (a radius just above the separation so the pair is "in")
+    code, s64 = oracle.pair(ra1, dec1, ra2, dec2, min(max(exact * 1.5, 1e-3), 648000.0))
+    assert code in (oracle.IN_FP64, oracle.IN_QUAD, oracle.IN_TIE)
+    assert abs(s64 - exact) <= 1e-12 + 1e-14 * exact, (name, s64, exact)
+    # binary128 path
+    sq = oracle.sep_q(ra1, dec1, ra2, dec2)
+    assert abs(sq - exact) <= 1e-12 + 4e-16 * exact, (name, sq, exact)
+    # symmetric in the two points
+    assert oracle.sep_q(ra2, dec2, ra1, dec1) == sq
+
+
+def _exact_in(sep_exact: Fraction, r_arcsec: float) -> bool:
+    return sep_exact <= Fraction(r_arcsec) / 3600
+
+
+def _decisions_match(ra1, dec1, ra2, dec2, r, truth):
+    code, _ = oracle.pair(ra1, dec1, ra2, dec2, r)
+    got = code in (oracle.IN_FP64, oracle.IN_QUAD, oracle.IN_TIE)
+    assert got == truth, (ra1, dec1, ra2, dec2, r, code, truth)
+    assert oracle.pair_q(ra1, dec1, ra2, dec2, r) == truth
+    return code
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 2.0, 3.515625, 5.0, 0.87890625])
+def test_meridian_threshold_exact(r):
+    """Same RA: theta = |dDec| exactly. B at dDec = r then +-k ulp."""
+    g = np.random.default_rng(11)
+    rdeg = r / 3600.0
+    codes = []
+    for _ in range(40):
+        ra = float(g.uniform(0, 360))
+        dec = float(g.uniform(-80, 80))
+        d2 = dec + rdeg
+        for k in range(-3, 4):
+            dd = d2
+            for _ in range(abs(k)):
+                dd = np.nextafter(dd, math.inf if k > 0 else -math.inf)
+            sep = abs(Fraction(dd) - Fraction(dec))
+            codes.append(_decisions_match(ra, dec, ra, float(dd), r, _exact_in(sep, r)))
+    # dyadic radii give exact ties on the meridian; they must be counted in
+    if r in (3.515625, 0.87890625):
+        assert oracle.IN_TIE in codes
+
+
+@pytest.mark.parametrize("r", [0.5, 2.0, 3.515625])
+def test_equator_threshold_exact(r):
+    """dec = 0 on both sides: theta = |dRA| (folded) exactly."""
+    g = np.random.default_rng(12)
+    rdeg = r / 3600.0
+    for _ in range(40):
+        ra = float(g.uniform(0, 360))
+        for sgn in (1, -1):
+            r2 = ra + sgn * rdeg
+            for k in range(-2, 3):
+                x = r2
+                for _ in range(abs(k)):
+                    x = np.nextafter(x, math.inf if k > 0 else -math.inf)
+                x = float(x)
+                if x < 0:
+                    x += 360.0
+                if x > 360.0:
+                    x -= 360.0
+                d = abs(Fraction(x) - Fraction(ra))
+                d = min(d, 360 - d)
+                _decisions_match(ra, 0.0, x, 0.0, r, _exact_in(d, r))
+
+
+@pytest.mark.parametrize("r", [1.0, 3.515625])
+def test_crosspole_threshold_exact(r):
+    """RAs 180 apart in one hemisphere: theta = 180 - |dec1| - |dec2| exactly."""
+    g = np.random.default_rng(13)
+    rdeg = r / 3600.0
+    for _ in range(30):
+        ra = float(g.uniform(0, 180))
+        hemi = 1.0 if g.random() < 0.5 else -1.0
+        x1 = float(g.uniform(0, rdeg))
+        dec1 = hemi * (90.0 - x1)
+        d2 = 90.0 - (rdeg - (90.0 - abs(dec1)))
+        for k in range(-2, 3):
+            dd = d2
+            for _ in range(abs(k)):
+                dd = np.nextafter(dd, math.inf if k > 0 else -math.inf)
+            dd = min(float(dd), 90.0)
+            sep = (90 - abs(Fraction(dec1))) + (90 - Fraction(dd))
+            _decisions_match(ra, dec1, ra + 180.0, hemi * dd, r, _exact_in(sep, r))
+
+
+def test_generic_threshold_against_decimal():
+    """Random geometry, B placed at ~r then nudged; truth from 60-digit decimal."""
+    g = synth.rng(900, 0)
+    n = 60
+    ra, dec = synth.uniform_sphere(g, n)
+    dec = np.clip(dec, -89.9, 89.9)
+    for r in (0.5, 2.0, 5.0):
+        rdeg = r / 3600.0
+        for f in (1 - 1e-6, 1 - 1e-12, 1.0, 1 + 1e-12, 1 + 1e-6):
+            b_ra, b_dec = synth.direct(ra, dec, np.full(n, rdeg * f), g.uniform(0, 2 * math.pi, n))
+            for i in range(n):
+                truth = hp.within(ra[i], dec[i], b_ra[i], b_dec[i], r)
+                code, s = oracle.pair(ra[i], dec[i], b_ra[i], b_dec[i], r)
+                got = code in (oracle.IN_FP64, oracle.IN_QUAD, oracle.IN_TIE)
+                assert got == truth, (i, r, f, code)
+
+
+def test_separation_accuracy_against_decimal():
+    """|sep - sep_exact| within 1e-12 arcsec + 1e-14 relative, 1e-6'' .. 1 deg."""
+    g = synth.rng(901, 0)
+    n = 30
+    ra, dec = synth.uniform_sphere(g, n)
+    for sep_as in (1e-6, 1e-3, 0.3, 1.0, 2.0, 10.0, 300.0, 3600.0):
+        b_ra, b_dec = synth.direct(ra, dec, np.full(n, sep_as / 3600.0), g.uniform(0, 2 * math.pi, n))
+        for i in range(n):
+            exact = float(hp.sep_arcsec(ra[i], dec[i], b_ra[i], b_dec[i]))
+            code, s = oracle.pair(ra[i], dec[i], b_ra[i], b_dec[i], 3600.0 * 2)
+            assert code != oracle.OUT
+            assert abs(s - exact) <= 1e-12 + 1e-14 * exact, (sep_as, s, exact)
+            assert abs(oracle.sep_q(ra[i], dec[i], b_ra[i], b_dec[i]) - exact) <= 1e-15 + 4e-16 * exact
+
+
+KINDS = ["random", "pole", "seam", "grid", "dup", "same", "dense"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_zone_join_matches_brute_force(kind, seed):
+    for r in (0.5, 2.0, 7.0):
+        a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 600, seed, r)
+        z = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        bf = oracle.brute(a_ra, a_dec, b_ra, b_dec, r)
+        assert len(z) == len(bf)
+        assert np.array_equal(z.keys(), bf.keys())
+        assert np.array_equal(z.sep, bf.sep)
+
+
+def test_zone_join_brute_force_large_radius():
+    """Radius of an arc-minute or more: many zones per window, wide RA windows."""
+    g = synth.rng(902, 0)
+    a_ra, a_dec = synth.polar_caps(g, 800, 2.0)
+    b_ra, b_dec = synth.polar_caps(g, 800, 2.0)
+    for r in (60.0, 900.0, 3600.0):
+        z = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        bf = oracle.brute(a_ra, a_dec, b_ra, b_dec, r)
+        assert np.array_equal(z.keys(), bf.keys()), r
+        assert len(z) > 0
+
+
+def _pairset(res):
+    return res.keys()
+
+
+def test_invariants_swap_shift_reflect():
+    g = synth.rng(903, 0)
+    for kind in ("seam", "pole", "dense", "grid"):
+        a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 1500, 7, 2.0)
+        a_ra, a_dec, b_ra, b_dec = (synth.quantize(x) for x in (a_ra, a_dec, b_ra, b_dec))
+        a_ra[a_ra >= 360.0] = 0.0
+        b_ra[b_ra >= 360.0] = 0.0
+        r = 2.0
+        base = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        assert len(base) > 0
+        # swap A and B: the transposed set, identical separations
+        sw = oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r)
+        t = (sw.b.astype(np.uint64) << np.uint64(32)) | sw.a.astype(np.uint64)
+        order = np.argsort(t)
+        assert np.array_equal(t[order], base.keys())
+        assert np.array_equal(sw.sep[order], base.sep)
+        # RA rotation by a multiple of 2^-30 deg (exact on the quantised grid)
+        for shift in (2.0 ** -30 * 12345, 180.0, 359.5):
+            ar = np.mod(a_ra + shift, 360.0)
+            br = np.mod(b_ra + shift, 360.0)
+            assert np.array_equal(np.mod(ar - shift, 360.0), a_ra)  # exact
+            rot = oracle.xmatch(ar, a_dec, br, b_dec, r)
+            assert np.array_equal(rot.keys(), base.keys()), (kind, shift)
+        # dec -> -dec and ra -> 360 - ra
+        fl = oracle.xmatch(a_ra, -a_dec, b_ra, -b_dec, r)
+        assert np.array_equal(fl.keys(), base.keys())
+        mi = oracle.xmatch(np.where(a_ra > 0, 360.0 - a_ra, 0.0), a_dec,
+                           np.where(b_ra > 0, 360.0 - b_ra, 0.0), b_dec, r)
+        assert np.array_equal(mi.keys(), base.keys())
+
+
+def test_patch_counts_match_expectation():
+    """Counterpart + chance pairs of the 100k patch workload (r = 1'')."""
+    c = synth.patch_pair()
+    res = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    sig = 0.3
+    p_in = 1.0 - math.exp(-1.0 / (2 * sig * sig))
+    exp_cp = 30000 * p_in
+    area_as2 = math.radians(10.0) * (math.sin(math.radians(10.0)) - 0.0) * (180 / math.pi * 3600) ** 2
+    exp_ch = 1e5 * (1e5 / area_as2) * math.pi * 1.0 ** 2
+    mean = exp_cp + exp_ch
+    var = 30000 * p_in * (1 - p_in) + exp_ch
+    assert abs(len(res) - mean) <= 5 * math.sqrt(var), (len(res), mean)
+    assert res.sep.max() <= 1.0 and res.sep.min() >= 0.0
+
+
+@pytest.mark.parametrize("bad", [(float("nan"), 0.0), (0.0, float("inf")), (-1e-300, 0.0),
+                                 (360.0000000001, 0.0), (10.0, 90.0000000001), (10.0, -91.0)])
+def test_invalid_positions_rejected(bad):
+    a_ra = np.array([1.0, bad[0]])
+    a_dec = np.array([1.0, bad[1]])
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch(a_ra, a_dec, np.array([1.0]), np.array([1.0]), 1.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch(np.array([1.0]), np.array([1.0]), a_ra, a_dec, 1.0)
+
+
+def test_bad_radius_and_empty():
+    one = np.array([1.0])
+    for r in (0.0, -1.0, float("nan"), 3600.5):
+        with pytest.raises(oracle.OracleError):
+            oracle.xmatch(one, one, one, one, r)
+    e = np.array([], dtype=np.float64)
+    assert len(oracle.xmatch(e, e, one, one, 1.0)) == 0
+    assert len(oracle.xmatch(one, one, e, e, 1.0)) == 0
+
+
+def test_ra_360_is_ra_0():
+    res = oracle.xmatch(np.array([360.0]), np.array([5.0]), np.array([0.0]), np.array([5.0]), 0.1)
+    assert len(res) == 1 and res.sep[0] == 0.0

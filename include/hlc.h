@@ -1,0 +1,165 @@
+/* hlc.h -- C ABI of the MI355X (gfx950) positional cross-match library.
+ *
+ * The operation (paper, section 2.1): given two catalogues A and B of sky
+ * positions (right ascension, declination, both in degrees) and a radius r,
+ * report every pair (i, j) whose great-circle separation (the angle of
+ * eq. (1)) is at most r. The comparison is inclusive, as in eq. (4), and all
+ * pairs are reported, not only the nearest one (section 4.3.2 keeps a result
+ * for every catalogue pair). The paper's eq. (4) threshold 3*sqrt(r1^2+r2^2)
+ * is passed as r by the caller.
+ *
+ * Semantics shared by every entry point
+ *   - Inputs are FP64 degrees read as exact reals: RA in [0, 360] (360 is the
+ *     same point as 0), Dec in [-90, 90], finite. Anything else is rejected
+ *     with HLC_E_INVAL (detected on the device; the output buffers and the
+ *     pair count are then unspecified).
+ *   - The result is a set: pair order is unspecified. Each pair carries the
+ *     indices into the caller's ORIGINAL arrays and, unless HLC_NO_SEP is
+ *     set, the separation in arcsec as FP64 (within 1e-9 arcsec of the exact
+ *     value).
+ *   - The pair set is exact: a pair is reported iff its exact separation is
+ *     <= r_arcsec/3600 degrees, where pairs within a relative 1e-28 of r
+ *     (indistinguishable at double-double precision) count as matches.
+ *   - r_arcsec must lie in (0, 3600]; 0 <= na, nb < 2^31.
+ *   - A and B may be the same arrays; they are still two catalogues, so
+ *     (i, i) is reported with separation 0.
+ *
+ * Memory and ownership
+ *   - Coordinate and output pointers are DEVICE pointers (hipMalloc'd, or a
+ *     torch tensor's data_ptr()) unless a name says _host.
+ *   - The caller owns all input and output buffers; the library never keeps
+ *     a caller pointer after a call returns.
+ *   - The library owns a per-device workspace, grown on demand and released
+ *     by hlc_shutdown(), and every hlc_part it hands out.
+ *
+ * Errors: every int-returning call returns HLC_OK (0) or a negative
+ * hlc_status; no C++ exception crosses this boundary. HIP runtime failures
+ * map to HLC_E_DEVICE. Calls are synchronous on opts->stream (they return
+ * once the pair count is known) and are not thread-safe with each other.
+ */
+#ifndef HLC_H_
+#define HLC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HLC_OK = 0,
+  HLC_E_INVAL = -1,       /* bad argument or coordinate                           */
+  HLC_E_NOMEM = -2,       /* device or host allocation failed                     */
+  HLC_E_OVERFLOW = -3,    /* more pairs than opts->capacity; *n_pairs = required  */
+  HLC_E_DEVICE = -4,      /* HIP runtime error                                    */
+  HLC_E_UNSUPPORTED = -5  /* valid request this build does not handle             */
+} hlc_status;
+
+/* Filter precision. Both give the same exact pair set; they differ in speed.
+ *   HLC_FP32_RECHECK: candidate filter in FP32 on offsets from per-cell
+ *     centres, every candidate certified in FP64 (default).
+ *   HLC_FP64: candidate filter in FP64 on unit vectors.                     */
+typedef enum { HLC_FP32_RECHECK = 0, HLC_FP64 = 1 } hlc_precision;
+
+/* Output record: indices into the caller's original A and B arrays. */
+typedef struct {
+  uint32_t a, b;
+} hlc_pair;
+
+/* opts->flags */
+#define HLC_NO_SEP 0x1u   /* do not write separations (out_sep may be NULL)    */
+#define HLC_PROFILE 0x2u  /* time each stage with HIP events (hlc_last_stats)  */
+#define HLC_SORTED 0x4u   /* reserved: sorted output is not implemented        */
+
+/* Optional fixed tuning; zero fields mean "choose automatically". */
+typedef struct hlc_tuning {
+  double zone_height_arcsec; /* Dec zone height; >= 2.0001 r is enforced       */
+  int32_t ra_cell_bins_log2; /* log2 of RA bins per FP32 cell (0 = auto)       */
+  int32_t reserved[6];
+} hlc_tuning;
+
+typedef struct hlc_opts {
+  hlc_precision precision;
+  void *stream;              /* hipStream_t; NULL = the null stream            */
+  int64_t capacity;          /* length of out_pairs / out_sep, in pairs        */
+  int64_t *n_pairs;          /* host pointer; out: pairs found (or required)  */
+  uint32_t flags;            /* HLC_NO_SEP | HLC_PROFILE                       */
+  const hlc_tuning *tuning;  /* NULL = automatic                               */
+} hlc_opts;
+
+/* Per-call statistics of the last call on this thread's library context. */
+typedef struct hlc_stats {
+  int64_t na, nb;            /* catalogue sizes                               */
+  int64_t nb_halo;           /* B entries after Dec-halo duplication          */
+  int64_t n_pairs;           /* pairs in the result                            */
+  int64_t n_candidates;      /* filter survivors sent to certification        */
+  int64_t n_band;            /* candidates re-evaluated from (ra, dec) in FP64 */
+  int64_t n_ties;            /* candidates decided in double-double            */
+  int32_t n_zones;           /* Dec zones                                      */
+  int32_t ra_bits;           /* RA bins = 2^ra_bits                            */
+  double zone_height_arcsec;
+  /* stage times in milliseconds (HLC_PROFILE only, else 0) */
+  double t_keygen_ms, t_sort_ms, t_layout_ms, t_ranges_ms, t_match_ms, t_certify_ms, t_total_ms;
+  double reserved[8];
+} hlc_stats;
+
+/* Cross-match A against B at radius r_arcsec (the paper's section 3.1 kernel
+ * module and section 4.2 two-level partition, redesigned for one GPU).
+ *   a_ra, a_dec [na], b_ra, b_dec [nb]: device FP64 degrees.
+ *   out_pairs [opts->capacity]: device; out_sep [opts->capacity]: device FP64
+ *     arcsec, or NULL with HLC_NO_SEP.
+ *   *opts->n_pairs receives the pair count. If it exceeds opts->capacity the
+ *     call returns HLC_E_OVERFLOW, *n_pairs holds the exact required count
+ *     and the buffers' contents are unspecified.
+ *   opts may be NULL only when capacity is irrelevant: it is required.       */
+int hlc_xmatch(const double *a_ra, const double *a_dec, int64_t na, const double *b_ra,
+               const double *b_dec, int64_t nb, double r_arcsec, hlc_pair *out_pairs,
+               double *out_sep_arcsec, const hlc_opts *opts);
+
+/* Reusable device index of one catalogue (section 4.2's first-level
+ * partition: positions grouped by Dec zone, then RA). An index built for
+ * radius r can serve as either side of hlc_xmatch_part at any radius <= r
+ * built with the same zone height. Free with hlc_part_free.                 */
+struct hlc_part;
+int hlc_partition(const double *ra_deg, const double *dec_deg, int64_t n, double r_arcsec,
+                  const hlc_opts *opts, struct hlc_part **out);
+void hlc_part_free(struct hlc_part *part);
+int hlc_xmatch_part(const struct hlc_part *A, const struct hlc_part *B, double r_arcsec,
+                    hlc_pair *out_pairs, double *out_sep_arcsec, const hlc_opts *opts);
+
+/* Many independent jobs in one call (section 4.3.1's launch geometry applied
+ * to thousands of calculation blocks at once). Job j matches
+ * A[a_off, a_off+na) against B[b_off, b_off+nb) at radius r_arcsec.
+ *   jobs [njobs]: HOST array. a_ra..b_dec: device arrays holding all jobs.
+ *   out_pairs / out_sep: device, capacity opts->capacity; pair indices are
+ *     GLOBAL (into the packed arrays).
+ *   job_pair_count [njobs]: device int64, pairs found per job (may be NULL).
+ * Total pairs go to *opts->n_pairs; overflow behaves as in hlc_xmatch.     */
+typedef struct hlc_job {
+  int64_t a_off, na, b_off, nb;
+  double r_arcsec;
+} hlc_job;
+int hlc_xmatch_batch(const hlc_job *jobs, int32_t njobs, const double *a_ra, const double *a_dec,
+                     const double *b_ra, const double *b_dec, hlc_pair *out_pairs,
+                     double *out_sep_arcsec, int64_t *job_pair_count, const hlc_opts *opts);
+
+/* Catalogues in pinned HOST memory, streamed to the device in Dec chunks
+ * (section 4.3.1: several streams overlap copies and compute; section 4.3.2:
+ * page-locked host memory). Pairs are delivered through `sink` in batches
+ * from a bounded device ring; `sink` returns 0 to continue, non-zero to
+ * abort (the call then returns HLC_E_INVAL). opts->capacity is the ring size
+ * in pairs (0 = default); opts->n_pairs receives the total.                 */
+typedef int (*hlc_sink)(const hlc_pair *pairs, const double *sep_arcsec, int64_t n, void *user);
+int hlc_xmatch_stream(const double *a_ra_host, const double *a_dec_host, int64_t na,
+                      const double *b_ra_host, const double *b_dec_host, int64_t nb,
+                      double r_arcsec, hlc_sink sink, void *user, const hlc_opts *opts);
+
+const char *hlc_strerror(int status);
+int hlc_last_stats(hlc_stats *out);
+void hlc_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLC_H_ */

@@ -1,0 +1,186 @@
+"""Python binding of libhlc, the gfx950 positional cross-match library.
+
+Argument marshalling only: every step of the cross-match runs in the HIP
+kernels of ``libhlc.so`` (see ``include/hlc.h`` for the C ABI). PyTorch is
+used for device memory and the current HIP stream. There is no CPU fallback:
+if the library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhlc.so")
+
+HLC_OK, HLC_E_INVAL, HLC_E_NOMEM, HLC_E_OVERFLOW, HLC_E_DEVICE, HLC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+HLC_FP32_RECHECK, HLC_FP64 = 0, 1
+HLC_NO_SEP, HLC_PROFILE, HLC_SORTED = 0x1, 0x2, 0x4
+
+EXPORTS = ["hlc_xmatch", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
+           "hlc_xmatch_stream", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
+
+
+class hlc_tuning(C.Structure):
+    _fields_ = [("zone_height_arcsec", C.c_double), ("ra_cell_bins_log2", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class hlc_opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("stream", C.c_void_p), ("capacity", C.c_int64),
+                ("n_pairs", C.POINTER(C.c_int64)), ("flags", C.c_uint32),
+                ("tuning", C.POINTER(hlc_tuning))]
+
+
+class hlc_stats(C.Structure):
+    _fields_ = [("na", C.c_int64), ("nb", C.c_int64), ("nb_halo", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_candidates", C.c_int64), ("n_band", C.c_int64), ("n_ties", C.c_int64),
+                ("n_zones", C.c_int32), ("ra_bits", C.c_int32), ("zone_height_arcsec", C.c_double),
+                ("t_keygen_ms", C.c_double), ("t_sort_ms", C.c_double), ("t_layout_ms", C.c_double),
+                ("t_ranges_ms", C.c_double), ("t_match_ms", C.c_double), ("t_certify_ms", C.c_double),
+                ("t_total_ms", C.c_double), ("reserved", C.c_double * 8)]
+
+
+class hlc_job(C.Structure):
+    _fields_ = [("a_off", C.c_int64), ("na", C.c_int64), ("b_off", C.c_int64), ("nb", C.c_int64),
+                ("r_arcsec", C.c_double)]
+
+
+SINK = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
+
+_lib = None
+
+
+class HLCError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})" if what else f"{strerror(status)} ({status})")
+
+
+def load() -> C.CDLL:
+    """Load libhlc.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = C.CDLL(LIB_PATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        lib.hlc_xmatch.restype = C.c_int
+        lib.hlc_xmatch.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, vp, vp, C.POINTER(hlc_opts)]
+        lib.hlc_partition.restype = C.c_int
+        lib.hlc_partition.argtypes = [vp, vp, i64, C.c_double, C.POINTER(hlc_opts), C.POINTER(vp)]
+        lib.hlc_part_free.restype = None
+        lib.hlc_part_free.argtypes = [vp]
+        lib.hlc_xmatch_part.restype = C.c_int
+        lib.hlc_xmatch_part.argtypes = [vp, vp, C.c_double, vp, vp, C.POINTER(hlc_opts)]
+        lib.hlc_xmatch_batch.restype = C.c_int
+        lib.hlc_xmatch_batch.argtypes = [C.POINTER(hlc_job), C.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                         C.POINTER(hlc_opts)]
+        lib.hlc_xmatch_stream.restype = C.c_int
+        lib.hlc_xmatch_stream.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, SINK, vp,
+                                          C.POINTER(hlc_opts)]
+        lib.hlc_strerror.restype = C.c_char_p
+        lib.hlc_strerror.argtypes = [C.c_int]
+        lib.hlc_last_stats.restype = C.c_int
+        lib.hlc_last_stats.argtypes = [C.POINTER(hlc_stats)]
+        lib.hlc_shutdown.restype = None
+        lib.hlc_shutdown.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().hlc_strerror(int(status)).decode()
+    except Exception:  # library not built
+        return f"status {status}"
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    return int(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_coords(*ts):
+    import torch
+    for t in ts:
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 1):
+            raise ValueError("coordinates must be contiguous 1-D float64 CUDA tensors")
+
+
+def make_opts(precision=HLC_FP32_RECHECK, capacity=0, stream=None, flags=0, tuning=None):
+    n = C.c_int64(0)
+    o = hlc_opts()
+    o.precision = int(precision)
+    o.stream = _stream_handle(stream)
+    o.capacity = int(capacity)
+    o.n_pairs = C.pointer(n)
+    o.flags = int(flags)
+    tu = None
+    if tuning:
+        tu = hlc_tuning()
+        tu.zone_height_arcsec = float(tuning.get("zone_height_arcsec", 0.0))
+        tu.ra_cell_bins_log2 = int(tuning.get("ra_cell_bins_log2", 0))
+        o.tuning = C.pointer(tu)
+    return o, n, tu
+
+
+def hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r_arcsec, out_pairs, out_sep, *, precision=HLC_FP32_RECHECK,
+               capacity=None, stream=None, flags=0, tuning=None):
+    """Call hlc_xmatch on torch CUDA tensors. Returns (status, n_pairs).
+
+    out_pairs: int32 tensor (capacity, 2); out_sep: float64 (capacity,) or None.
+    """
+    _check_coords(a_ra, a_dec, b_ra, b_dec)
+    if capacity is None:
+        capacity = 0 if out_pairs is None else out_pairs.shape[0]
+    o, n, tu = make_opts(precision, capacity, stream, flags, tuning)
+    st = load().hlc_xmatch(_ptr(a_ra), _ptr(a_dec), a_ra.numel(), _ptr(b_ra), _ptr(b_dec), b_ra.numel(),
+                           float(r_arcsec), _ptr(out_pairs), _ptr(out_sep), C.byref(o))
+    return st, n.value
+
+
+def xmatch(a_ra, a_dec, b_ra, b_dec, r_arcsec, *, precision=HLC_FP32_RECHECK, capacity=None,
+           stream=None, flags=0, tuning=None, want_sep=True):
+    """Allocate outputs, call hlc_xmatch, grow and retry once on overflow.
+
+    Returns (pairs[n, 2] int32 CUDA tensor, sep[n] float64 CUDA tensor or None).
+    """
+    import torch
+    dev = a_ra.device
+    cap = capacity if capacity is not None else max(1024, (a_ra.numel() + b_ra.numel()) // 2)
+    if not want_sep:
+        flags |= HLC_NO_SEP
+    for _ in range(2):
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        sep = torch.empty(cap, dtype=torch.float64, device=dev) if want_sep else None
+        st, n = hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r_arcsec, pairs, sep, precision=precision,
+                           capacity=cap, stream=stream, flags=flags, tuning=tuning)
+        if st == HLC_E_OVERFLOW:
+            cap = int(n * 1.05) + 16
+            continue
+        if st != HLC_OK:
+            raise HLCError(st, "hlc_xmatch")
+        return pairs[:n], (sep[:n] if want_sep else None)
+    raise HLCError(HLC_E_OVERFLOW, "hlc_xmatch")
+
+
+def last_stats() -> dict:
+    s = hlc_stats()
+    st = load().hlc_last_stats(C.byref(s))
+    if st != HLC_OK:
+        raise HLCError(st, "hlc_last_stats")
+    return {name: (getattr(s, name) if not isinstance(getattr(s, name), C.Array) else None)
+            for name, _ in hlc_stats._fields_ if name != "reserved"}
+
+
+def shutdown() -> None:
+    load().hlc_shutdown()

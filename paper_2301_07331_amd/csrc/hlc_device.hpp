@@ -1,0 +1,276 @@
+// hlc_device.hpp -- shared definitions of the gfx950 cross-match library:
+// the partition geometry, degree-argument trigonometry, double-double
+// arithmetic for threshold ties, and wave64 helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlc {
+
+// ---------------------------------------------------------------------------
+// Constants (double-double heads/tails printed by gen_constants.py).
+// ---------------------------------------------------------------------------
+constexpr double DEG2RAD_HI = 0x1.1df46a2529d39p-6;   // pi/180, head
+constexpr double DEG2RAD_LO = 0x1.5c1d8becdd291p-62;  // pi/180, tail
+constexpr double RAD2ARCSEC = 0x1.92dc67331ad7bp+17;  // 648000/pi rounded
+constexpr double EPS_BAND = 1e-13;                    // FP64 haversine certification band
+constexpr double TIE_REL = 1e-28;                     // double-double tie width
+constexpr uint32_t HALO_BIT = 0x80000000u;            // B entry is a Dec-halo copy
+constexpr uint32_t IDX_MASK = 0x7fffffffu;
+constexpr int GROUP = 16;                             // A sources per group (one DPP row)
+constexpr int MAXR = 4;                               // B ranges kept per group
+
+// Partition geometry of one call: Dec zones of height h, RA bins of width
+// 360/nbins; a source's key is (zone << rb) | bin. FP32 cells are
+// (zone, bin >> cell_shift).
+struct Geom {
+  double h_deg;       // zone height (deg)
+  double inv_h;       // 1 / h_deg
+  double bin_scale;   // nbins / 360
+  double r_deg;       // r_arcsec / 3600
+  double rpad_deg;    // r padded outward for windows and halos
+  int32_t nz;         // number of zones
+  int32_t rb;         // RA bits; nbins = 1 << rb
+  uint32_t nbins;
+  int32_t cell_shift; // FP32 cell = bin >> cell_shift
+  uint32_t nsuper;    // nbins >> cell_shift
+  int32_t pad_;
+};
+
+// Per-group B candidate ranges (positions in the sorted B arrays).
+struct GroupRanges {
+  uint32_t start[MAXR];
+  uint32_t end[MAXR];
+  uint32_t count;
+  float thr32;        // FP32 chord^2 acceptance threshold for this group
+  uint32_t pad_[2];
+};
+
+// Device-side counters, read back once per call.
+struct Counters {
+  unsigned long long n_halo;      // B halo copies appended by keygen
+  unsigned long long n_pairs;     // pairs found (may exceed capacity)
+  unsigned long long n_cand;      // filter survivors certified
+  unsigned long long n_band;      // entries in the band list
+  unsigned long long n_ties;      // decided in double-double
+  unsigned int err;               // bit 0: bad coordinate in A, bit 1: in B
+  unsigned int pad_;
+  unsigned long long pad2_[2];
+};
+
+struct Rec64 {      // FP64 working record (32 B)
+  double x, y, z;
+  uint32_t idx, pad;
+};
+struct Rec32 {      // FP32 working record (16 B): offset from the cell centre
+  float x, y, z;
+  uint32_t idx;
+};
+
+// ---------------------------------------------------------------------------
+// Geometry helpers (identical code for A and B keys, so they are monotone).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline bool valid_pos(double ra, double dec) {
+  // false for NaN as well
+  return (ra >= 0.0) && (ra <= 360.0) && (dec >= -90.0) && (dec <= 90.0);
+}
+
+__host__ __device__ inline int32_t zone_of(const Geom& g, double dec) {
+  double t = floor((dec + 90.0) * g.inv_h);
+  if (!(t >= 0.0)) return 0;
+  if (t > (double)(g.nz - 1)) return g.nz - 1;
+  return (int32_t)t;
+}
+
+__host__ __device__ inline uint32_t bin_of(const Geom& g, double ra) {
+  double t = floor(ra * g.bin_scale);
+  if (!(t >= 0.0)) return 0u;
+  if (t > (double)(g.nbins - 1)) return g.nbins - 1;
+  return (uint32_t)t;
+}
+
+__host__ __device__ inline uint32_t make_key(const Geom& g, int32_t z, uint32_t b) {
+  return ((uint32_t)z << g.rb) | b;
+}
+__host__ __device__ inline int32_t key_zone(const Geom& g, uint32_t k) { return (int32_t)(k >> g.rb); }
+__host__ __device__ inline uint32_t key_bin(const Geom& g, uint32_t k) { return k & (g.nbins - 1); }
+
+// ---------------------------------------------------------------------------
+// sin and cos of an angle in degrees, |x| <= 360.
+// The argument is reduced by the nearest multiple of 90 degrees, which is
+// exact in FP64 for |x| <= 360 (Sterbenz), converted to radians with a
+// double-double pi/180, and the quadrant is applied by swapping/negating.
+// ---------------------------------------------------------------------------
+__device__ inline void sincos_deg(double x, double* s, double* c) {
+  double q = rint(x * (1.0 / 90.0));
+  double y = fma(-q, 90.0, x);
+  double p = y * DEG2RAD_HI;
+  double e = fma(y, DEG2RAD_HI, -p);
+  double r = p + fma(y, DEG2RAD_LO, e);
+  double sr, cr;
+  sincos(r, &sr, &cr);
+  int qi = ((int)q) & 3;
+  if (qi == 0) { *s = sr; *c = cr; }
+  else if (qi == 1) { *s = cr; *c = -sr; }
+  else if (qi == 2) { *s = -sr; *c = -cr; }
+  else { *s = -cr; *c = sr; }
+}
+
+__device__ inline double cos_deg_abs(double dec) {
+  // cos of a declination, relatively accurate near the poles
+  double a = fabs(dec);
+  double s, c;
+  if (a <= 45.0) { sincos_deg(a, &s, &c); return c; }
+  sincos_deg(90.0 - a, &s, &c);
+  return s;
+}
+
+// RA difference folded into [-180, 180] without an extra rounding: the
+// larger value is first reduced by 360 (exact for values in [180, 360]).
+__device__ inline double dra_fold(double ra1, double ra2) {
+  if (fabs(ra1 - ra2) > 180.0) {
+    if (ra1 > ra2) ra1 -= 360.0; else ra2 -= 360.0;
+  }
+  return ra1 - ra2;
+}
+
+// Haversine h = sin^2(theta/2) in FP64 from degrees.
+__device__ inline double haversine64(double ra1, double dec1, double ra2, double dec2) {
+  double s1, c1, s2, c2;
+  sincos_deg(0.5 * (dec1 - dec2), &s1, &c1);
+  sincos_deg(0.5 * dra_fold(ra1, ra2), &s2, &c2);
+  return s1 * s1 + cos_deg_abs(dec1) * cos_deg_abs(dec2) * (s2 * s2);
+}
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic (value = hi + lo, |lo| <= ulp(hi)/2).
+// ---------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+
+__device__ inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ inline dd quick_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ inline dd dd_add(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  dd t = two_sum(x.lo, y.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+__device__ inline dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
+__device__ inline dd dd_mul(dd x, dd y) {
+  double p = x.hi * y.hi;
+  double e = fma(x.hi, y.hi, -p);
+  e = fma(x.hi, y.lo, e);
+  e = fma(x.lo, y.hi, e);
+  return quick_two_sum(p, e);
+}
+__device__ inline dd dd_mul_d(dd x, double y) {
+  double p = x.hi * y;
+  double e = fma(x.hi, y, -p);
+  e = fma(x.lo, y, e);
+  return quick_two_sum(p, e);
+}
+// x / n for an exactly representable n
+__device__ inline dd dd_div_d(dd x, double n) {
+  double q1 = x.hi / n;
+  double p = q1 * n;
+  double pe = fma(q1, n, -p);
+  dd r = dd_add(x, dd{-p, -pe});
+  double q2 = r.hi / n;
+  return quick_two_sum(q1, q2);
+}
+
+// sin and cos of a double-double angle in radians, |x| <= pi/2 + small.
+__device__ inline dd dd_sin(dd x) {
+  dd x2 = dd_mul(x, x);
+  dd term = x, sum = x;
+  for (int k = 1; k < 40; ++k) {
+    term = dd_div_d(dd_mul(term, x2), (double)((2 * k) * (2 * k + 1)));
+    term = dd_neg(term);
+    sum = dd_add(sum, term);
+    if (fabs(term.hi) <= 1e-36 * fabs(sum.hi)) break;
+  }
+  return sum;
+}
+__device__ inline dd dd_cos(dd x) {
+  dd x2 = dd_mul(x, x);
+  dd term = {1.0, 0.0}, sum = {1.0, 0.0};
+  for (int k = 1; k < 40; ++k) {
+    term = dd_div_d(dd_mul(term, x2), (double)((2 * k - 1) * (2 * k)));
+    term = dd_neg(term);
+    sum = dd_add(sum, term);
+    if (fabs(term.hi) <= 1e-36 * fabs(sum.hi)) break;
+  }
+  return sum;
+}
+__device__ inline dd dd_deg2rad(dd d) { return dd_mul(d, dd{DEG2RAD_HI, DEG2RAD_LO}); }
+
+// cos(dec) in double-double, relatively accurate near the poles.
+__device__ inline dd dd_cos_dec(double dec) {
+  double a = fabs(dec);
+  if (a <= 45.0) return dd_cos(dd_deg2rad(dd{a, 0.0}));
+  return dd_sin(dd_deg2rad(dd{90.0 - a, 0.0}));  // 90 - a exact
+}
+
+// Haversine in double-double.
+__device__ inline dd haversine_dd(double ra1, double dec1, double ra2, double dec2) {
+  dd ddec = two_sum(dec1, -dec2);
+  double a = ra1, b = ra2;
+  if (fabs(a - b) > 180.0) {
+    if (a > b) a -= 360.0; else b -= 360.0;  // exact
+  }
+  dd dra = two_sum(a, -b);
+  dd s1 = dd_sin(dd_mul_d(dd_deg2rad(ddec), 0.5));
+  dd s2 = dd_sin(dd_mul_d(dd_deg2rad(dra), 0.5));
+  dd cc = dd_mul(dd_cos_dec(dec1), dd_cos_dec(dec2));
+  return dd_add(dd_mul(s1, s1), dd_mul(cc, dd_mul(s2, s2)));
+}
+
+// sin^2(r/2) with r = r_arcsec / 3600 degrees, in double-double.
+__device__ inline dd threshold_dd(double r_arcsec) {
+  dd r = dd_div_d(dd{r_arcsec, 0.0}, 3600.0);
+  dd s = dd_sin(dd_mul_d(dd_deg2rad(r), 0.5));
+  return dd_mul(s, s);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of mask below this lane
+__device__ inline uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Broadcast lane n of each 16-lane row to the whole row (DPP row_newbcast).
+template <int N>
+__device__ inline float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + N, 0xf, 0xf, false));
+}
+template <int N>
+__device__ inline uint32_t row_bcast_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ inline double row_bcast(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x150 + N, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x150 + N, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+}  // namespace hlc

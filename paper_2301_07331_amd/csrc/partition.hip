@@ -1,0 +1,668 @@
+// partition.hip -- the first level of the cross-match: both catalogues are
+// grouped by declination zone and then by RA bin, on the GPU.
+//
+// The paper partitions on the CPU with HEALPix pixels and copies records that
+// lie near a pixel edge into the neighbouring pixel (section 3.2, Algorithm 1:
+// RA and Dec shifted by the error radius, so corners, the RA seam and the
+// 1/cos(Dec) stretch of RA near the poles can be missed). Here:
+//   * keys: zone z = floor((Dec + 90) / h), RA bin b = floor(RA * nbins / 360),
+//     key = (z << rb) | b (32 bits);
+//   * every B source is also keyed into the neighbouring zone when it lies
+//     within r of that zone (a Dec halo), so an A source needs B from its own
+//     zone only;
+//   * RA neighbourhoods are bin windows of half-width asin(sin r / cos Dec*)
+//     split at the 0/360 seam, and the whole zone ring within r of a pole;
+//   * keys are sorted with a stable LSD radix sort written here (8-bit digits,
+//     per-tile histograms, a device-wide scan, LDS-staged stable scatter).
+#include <hip/hip_runtime.h>
+
+#include "hlc_kernels.hpp"
+
+namespace hlc {
+
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 4096 keys per tile
+constexpr int RS_BINS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = RS_THREADS * SCAN_ITEMS;
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_zero_counters(Counters* c) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// keygen
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
+                                                const double* __restrict__ dec, uint32_t n,
+                                                Geom g, int halo, uint32_t err_bit,
+                                                uint32_t* __restrict__ keys,
+                                                uint32_t* __restrict__ vals, Counters* cnt) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool in = i < n;
+  double a = 0.0, d = 0.0;
+  if (in) {
+    a = ra[i];
+    d = dec[i];
+  }
+  bool ok = !in || valid_pos(a, d);
+  if (!ok) {
+    atomicOr(&cnt->err, err_bit);
+    a = 0.0;
+    d = 0.0;
+  }
+  int32_t z = zone_of(g, d);
+  uint32_t b = bin_of(g, a);
+  if (in) {
+    keys[i] = make_key(g, z, b);
+    vals[i] = i;
+  }
+  if (!halo) return;
+  // Dec halo: also key the source into the neighbouring zone when its
+  // padded Dec window reaches it (the zone height is >= 2 r, so at most one).
+  int32_t zl = zone_of(g, d - g.rpad_deg), zh = zone_of(g, d + g.rpad_deg);
+  int32_t other = (zl != z) ? zl : zh;
+  bool need = in && ok && other != z;
+  uint64_t m = __ballot(need);
+  if (m == 0) return;
+  uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(&cnt->n_halo, (unsigned long long)__popcll(m));
+  base = __shfl(base, (int)leader);
+  if (need) {
+    uint64_t pos = (uint64_t)n + base + rank_in(m);
+    keys[pos] = make_key(g, other, b);
+    vals[pos] = i | HALO_BIT;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort (8-bit digits)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                           uint32_t n, int shift,
+                                                           uint32_t* __restrict__ counts,
+                                                           uint32_t ntiles) {
+  __shared__ uint32_t h[4][RS_BINS];
+  const uint32_t t = threadIdx.x, w = t >> 6;
+  for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&h[0][0])[k] = 0u;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    uint32_t e = base + j * RS_THREADS + t;
+    if (e < n) atomicAdd(&h[w][(keys[e] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  counts[t * ntiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_w) {
+  const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t s = s_w[k];
+    if ((uint32_t)k < w) wbase += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                            uint32_t n, uint32_t* block_sums) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (base + j < n) s += in[base + j];
+  uint32_t tot;
+  block_exclusive_scan(s, &tot, s_w);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of nb values in place, any nb.
+__global__ __launch_bounds__(RS_THREADS) void k_scan_top(uint32_t* v, uint32_t nb) {
+  __shared__ uint32_t s_w[4];
+  uint32_t carry = 0;
+  for (uint32_t off = 0; off < nb; off += RS_THREADS) {
+    uint32_t i = off + threadIdx.x;
+    uint32_t x = i < nb ? v[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(x, &tot, s_w);
+    if (i < nb) v[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_scan_down(const uint32_t* in,
+                                                          uint32_t* out, uint32_t n,
+                                                          const uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  uint32_t x[SCAN_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    x[j] = (base + j < n) ? in[base + j] : 0u;
+    s += x[j];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, &tot, s_w) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += x[j];
+  }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, uint32_t n, int shift,
+    const uint32_t* __restrict__ offsets, uint32_t ntiles) {
+  __shared__ uint32_t s_k[RS_TILE];
+  __shared__ uint32_t s_v[RS_TILE];
+  __shared__ uint32_t s_wh[4][RS_BINS];
+  __shared__ uint32_t s_start[RS_BINS];
+  __shared__ uint32_t s_goff[RS_BINS];
+  __shared__ uint32_t s_w[4];
+  const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t tile = blockIdx.x;
+  const uint32_t base = tile * RS_TILE;
+  const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
+
+  for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
+  s_goff[t] = offsets[t * ntiles + tile];
+  __syncthreads();
+
+  // wave w owns tile elements [w*1024, (w+1)*1024), 64 per round
+  uint32_t key[RS_ITEMS], val[RS_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    uint32_t e = base + w * (RS_TILE / 4) + j * 64 + lane;
+    if (e < n) {
+      key[j] = keys_in[e];
+      val[j] = vals_in[e];
+      atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
+    } else {
+      key[j] = 0u;
+      val[j] = 0u;
+    }
+  }
+  __syncthreads();
+  {
+    const uint32_t d = t;
+    uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
+    uint32_t tot;
+    uint32_t st = block_exclusive_scan(c0 + c1 + c2 + c3, &tot, s_w);
+    s_start[d] = st;
+    s_wh[0][d] = st;
+    s_wh[1][d] = st + c0;
+    s_wh[2][d] = st + c0 + c1;
+    s_wh[3][d] = st + c0 + c1 + c2;
+  }
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    uint32_t e = base + w * (RS_TILE / 4) + j * 64 + lane;
+    bool valid = e < n;
+    uint32_t d = (key[j] >> shift) & 0xffu;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      uint64_t b = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? b : ~b;
+    }
+    if (valid) {
+      uint32_t rank = (uint32_t)__popcll(peers & lt);
+      uint32_t pos = s_wh[w][d] + rank;
+      s_k[pos] = key[j];
+      s_v[pos] = val[j];
+      // the highest lane of each digit group advances that digit's cursor
+      if ((peers >> lane) == 1ull) s_wh[w][d] += rank + 1u;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < tile_n; i += RS_THREADS) {
+    uint32_t k = s_k[i];
+    uint32_t d = (k >> shift) & 0xffu;
+    uint32_t gpos = s_goff[d] + (i - s_start[d]);
+    keys_out[gpos] = k;
+    vals_out[gpos] = s_v[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// zone / cell tables
+// ---------------------------------------------------------------------------
+__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double2* __restrict__ zone_cs,
+                              double2* __restrict__ super_cs) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (uint32_t)g.nz) {
+    const int32_t z = (int32_t)i;
+    double lo = -90.0 + (double)z * g.h_deg;
+    double hi = lo + g.h_deg;
+    // largest |Dec| a source assigned to this zone can have (padded for the
+    // rounding of the zone formula)
+    double dstar = fmin(fmax(fabs(lo), fabs(hi)) + 1e-9, 90.0);
+    int32_t m = -1;  // -1: whole zone ring
+    if (dstar + g.rpad_deg < 90.0) {
+      double ss, cs, sd, cd;
+      sincos_deg(g.rpad_deg, &ss, &cs);
+      sincos_deg(dstar, &sd, &cd);
+      double x = ss / cd;
+      if (x < 0.99) {
+        double delta = asin(x) * (180.0 / M_PI) * (1.0 + 1e-9) + 1e-12;
+        double mm = ceil(delta * g.bin_scale) + 2.0;
+        if (2.0 * mm + 1.0 < (double)g.nbins) m = (int32_t)mm;
+      }
+    }
+    zmarg[z] = m;
+    double mid = fmin(fmax(-90.0 + ((double)z + 0.5) * g.h_deg, -90.0), 90.0);
+    double s, c;
+    sincos_deg(mid, &s, &c);
+    zone_cs[z] = make_double2(c, s);
+  }
+  if (super_cs != nullptr && i < g.nsuper) {
+    double mid = ((double)i + 0.5) * (360.0 / (double)g.nsuper);
+    double s, c;
+    sincos_deg(mid, &s, &c);
+    super_cs[i] = make_double2(c, s);
+  }
+}
+
+__device__ inline uint32_t lower_bound_u32(const uint32_t* keys, uint32_t lo, uint32_t hi, uint32_t K) {
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] < K) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// zstart[z] = first position of zone z in the sorted keys; zstart[nz] = n
+__global__ void k_zone_starts(const uint32_t* __restrict__ keys, uint32_t n, Geom g,
+                              uint32_t* __restrict__ zstart) {
+  uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z > (uint32_t)g.nz) return;
+  if (z == (uint32_t)g.nz) { zstart[z] = n; return; }
+  zstart[z] = lower_bound_u32(keys, 0, n, (uint32_t)z << g.rb);
+}
+
+// ---------------------------------------------------------------------------
+// working layouts
+// ---------------------------------------------------------------------------
+__device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
+  double sd, cd, sa, ca;
+  sincos_deg(dec, &sd, &cd);
+  sincos_deg(ra, &sa, &ca);
+  x = cd * ca;
+  y = cd * sa;
+  z = sd;
+}
+
+__global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ vals, uint32_t n,
+                                                  const double* __restrict__ ra,
+                                                  const double* __restrict__ dec,
+                                                  Rec64* __restrict__ rec) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t v = vals[p];
+  uint32_t i = v & IDX_MASK;
+  double x, y, z;
+  unit_vector(ra[i], dec[i], x, y, z);
+  Rec64 r;
+  r.x = x;
+  r.y = y;
+  r.z = z;
+  r.idx = v;
+  r.pad = 0u;
+  rec[p] = r;
+}
+
+__device__ inline double snap20(double v) { return rint(v * 1048576.0) * (1.0 / 1048576.0); }
+
+// Centre of the FP32 cell holding key k, snapped to a 2^-20 grid so that
+// differences of two centres are exact in FP32.
+__device__ inline void cell_centre(const Geom& g, const double2* zone_cs, const double2* super_cs,
+                                   uint32_t k, double& cx, double& cy, double& cz) {
+  double2 zc = zone_cs[key_zone(g, k)];
+  double2 sc = super_cs[key_bin(g, k) >> g.cell_shift];
+  cx = snap20(zc.x * sc.x);
+  cy = snap20(zc.x * sc.y);
+  cz = snap20(zc.y);
+}
+
+__global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ keys,
+                                                  const uint32_t* __restrict__ vals, uint32_t n,
+                                                  const double* __restrict__ ra,
+                                                  const double* __restrict__ dec, Geom g,
+                                                  const double2* __restrict__ zone_cs,
+                                                  const double2* __restrict__ super_cs,
+                                                  Rec32* __restrict__ rec,
+                                                  double2* __restrict__ radec) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t v = vals[p];
+  uint32_t i = v & IDX_MASK;
+  double a = ra[i], d = dec[i];
+  double x, y, z, cx, cy, cz;
+  unit_vector(a, d, x, y, z);
+  cell_centre(g, zone_cs, super_cs, keys[p], cx, cy, cz);
+  Rec32 r;
+  r.x = (float)(x - cx);
+  r.y = (float)(y - cy);
+  r.z = (float)(z - cz);
+  r.idx = v;
+  rec[p] = r;
+  radec[p] = make_double2(a, d);
+}
+
+// ---------------------------------------------------------------------------
+// merge path: lb[i] = number of B keys strictly below keysA[i]
+// ---------------------------------------------------------------------------
+constexpr int MP_THREADS = 256;
+constexpr int MP_ITEMS = 8;
+constexpr int MP_TILE = MP_THREADS * MP_ITEMS;
+
+// number of A elements among the first d merged elements (A first on ties)
+__device__ inline uint32_t merge_split(const uint32_t* A, uint32_t na, const uint32_t* B, uint32_t nb,
+                                       uint32_t d) {
+  uint32_t lo = d > nb ? d - nb : 0u;
+  uint32_t hi = d < na ? d : na;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[d - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(MP_THREADS) void k_merge_lb(const uint32_t* __restrict__ A, uint32_t na,
+                                                         const uint32_t* __restrict__ B, uint32_t nb,
+                                                         uint32_t* __restrict__ lb) {
+  __shared__ uint32_t sA[MP_TILE];
+  __shared__ uint32_t sB[MP_TILE];
+  __shared__ uint32_t s_split[2];
+  const uint64_t total = (uint64_t)na + nb;
+  const uint32_t d0 = blockIdx.x * MP_TILE;
+  const uint32_t d1 = (uint32_t)min((uint64_t)d0 + MP_TILE, total);
+  if (threadIdx.x < 2) s_split[threadIdx.x] = merge_split(A, na, B, nb, threadIdx.x == 0 ? d0 : d1);
+  __syncthreads();
+  const uint32_t i0 = s_split[0], i1 = s_split[1];
+  const uint32_t j0 = d0 - i0, j1 = d1 - i1;
+  const uint32_t la = i1 - i0, lb_ = j1 - j0;
+  for (uint32_t k = threadIdx.x; k < la; k += MP_THREADS) sA[k] = A[i0 + k];
+  for (uint32_t k = threadIdx.x; k < lb_; k += MP_THREADS) sB[k] = B[j0 + k];
+  __syncthreads();
+  const uint32_t dl = threadIdx.x * MP_ITEMS;
+  if (dl >= la + lb_) return;
+  uint32_t ia = merge_split(sA, la, sB, lb_, dl);
+  uint32_t jb = dl - ia;
+  const uint32_t steps = min((uint32_t)MP_ITEMS, la + lb_ - dl);
+  for (uint32_t s = 0; s < steps; ++s) {
+    bool takeA = ia < la && (jb >= lb_ || sA[ia] <= sB[jb]);
+    if (takeA) {
+      lb[i0 + ia] = j0 + jb;
+      ++ia;
+    } else {
+      ++jb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-group B ranges
+// ---------------------------------------------------------------------------
+// first p in [lo, hi] with keys[p] >= K (hi if none), searching from `hint`
+__device__ inline uint32_t gallop_lower(const uint32_t* keys, uint32_t K, uint32_t hint, uint32_t lo,
+                                        uint32_t hi) {
+  if (hint < lo) hint = lo;
+  if (hint > hi) hint = hi;
+  int64_t l, r;
+  if (hint < hi && keys[hint] < K) {
+    int64_t a = hint, step = 1, b = a + 1;
+    while (b < (int64_t)hi && keys[b] < K) {
+      a = b;
+      step <<= 1;
+      b = a + step;
+    }
+    if (b > (int64_t)hi) b = hi;
+    l = a + 1;
+    r = b;
+  } else {
+    int64_t b = hint, step = 1, a = b - 1;
+    while (a >= (int64_t)lo && keys[a] >= K) {
+      b = a;
+      step <<= 1;
+      a = b - step;
+    }
+    l = a < (int64_t)lo ? (int64_t)lo : a + 1;
+    r = b;
+  }
+  while (l < r) {
+    int64_t mid = (l + r) >> 1;
+    if (keys[mid] >= K) r = mid; else l = mid + 1;
+  }
+  return (uint32_t)l;
+}
+
+// first p in [lo, hi] with keys[p] > K
+__device__ inline uint32_t gallop_upper(const uint32_t* keys, uint32_t K, uint32_t hint, uint32_t lo,
+                                        uint32_t hi) {
+  if (K == 0xffffffffu) return hi;
+  return gallop_lower(keys, K + 1u, hint, lo, hi);
+}
+
+struct RangeList {
+  uint32_t s[3 * GROUP];
+  uint32_t e[3 * GROUP];
+  int n;
+  __device__ void add(uint32_t a, uint32_t b) {
+    if (a >= b) return;
+    if (n > 0 && a <= e[n - 1]) {  // overlapping or touching the previous one
+      if (b > e[n - 1]) e[n - 1] = b;
+      return;
+    }
+    s[n] = a;
+    e[n] = b;
+    ++n;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keysA, uint32_t na,
+                                                const uint32_t* __restrict__ lb,
+                                                const uint32_t* __restrict__ keysB, uint32_t nb,
+                                                const uint32_t* __restrict__ zstartB,
+                                                const int32_t* __restrict__ zmarg, Geom g,
+                                                double c_r, GroupRanges* __restrict__ out,
+                                                uint32_t ngroups) {
+  uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (grp >= ngroups) return;
+  const uint32_t p0 = grp * GROUP;
+  const uint32_t cnt = min((uint32_t)GROUP, na - p0);
+  uint32_t k[GROUP];
+  for (uint32_t q = 0; q < cnt; ++q) k[q] = keysA[p0 + q];
+  RangeList L;
+  L.n = 0;
+  const int64_t nbins = g.nbins;
+  bool full_any = false;
+  int64_t ra_lo = INT64_MAX, ra_hi = INT64_MIN;  // unwrapped bin extent of all windows
+  uint32_t q = 0;
+  while (q < cnt) {
+    const int32_t z = key_zone(g, k[q]);
+    uint32_t qe = q;
+    while (qe + 1 < cnt && key_zone(g, k[qe + 1]) == z) ++qe;
+    const uint32_t zs = zstartB[z], ze = zstartB[z + 1];
+    const int64_t bf = key_bin(g, k[q]), bl = key_bin(g, k[qe]);
+    const int32_t m = zmarg[z];
+    const int64_t lo = bf - m, hi = bl + m;
+    if (m < 0 || hi - lo + 1 >= nbins) {
+      full_any = true;
+      L.add(zs, ze);
+    } else if (zs < ze) {
+      uint32_t s = gallop_lower(keysB, make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)), lb[p0 + q], zs, ze);
+      uint32_t e = gallop_upper(keysB, make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)),
+                                lb[p0 + qe], zs, ze);
+      if (hi > nbins - 1) {  // window passes RA 360: low bins of the zone
+        uint32_t e2 = gallop_upper(keysB, make_key(g, z, (uint32_t)(hi - nbins)), zs, zs, ze);
+        L.add(zs, e2);
+      }
+      L.add(s, e);
+      if (lo < 0) {  // window passes RA 0: high bins of the zone
+        uint32_t s2 = gallop_lower(keysB, make_key(g, z, (uint32_t)(nbins + lo)), ze, zs, ze);
+        L.add(s2, ze);
+      }
+    }
+    if (lo < ra_lo) ra_lo = lo;
+    if (hi > ra_hi) ra_hi = hi;
+    q = qe + 1;
+  }
+  // keep at most MAXR ranges by merging across the smallest gaps
+  while (L.n > MAXR) {
+    int best = 0;
+    uint32_t gap = 0xffffffffu;
+    for (int t = 0; t + 1 < L.n; ++t) {
+      uint32_t gp = L.s[t + 1] - L.e[t];
+      if (gp < gap) { gap = gp; best = t; }
+    }
+    L.e[best] = L.e[best + 1];
+    for (int t = best + 1; t + 1 < L.n; ++t) {
+      L.s[t] = L.s[t + 1];
+      L.e[t] = L.e[t + 1];
+    }
+    --L.n;
+  }
+  GroupRanges R;
+  for (int t = 0; t < MAXR; ++t) {
+    R.start[t] = t < L.n ? L.s[t] : 0u;
+    R.end[t] = t < L.n ? L.e[t] : 0u;
+  }
+  R.count = (uint32_t)L.n;
+  // FP32 acceptance threshold: bound E on |u - c0| over the group's window
+  // (Dec span + RA span + two cell diagonals, as arcs >= chords), then
+  // chord_fp32 <= chord + 8 * 2^-24 * E (see the error budget in match.hip).
+  const int32_t z0 = key_zone(g, k[0]), z1 = key_zone(g, k[cnt - 1]);
+  double span_dec = (double)(z1 - z0 + 1) * g.h_deg + 2.0 * g.rpad_deg;
+  double span_ra = full_any ? 360.0 : fmin(360.0, (double)(ra_hi - ra_lo + 1) / g.bin_scale);
+  double cell = g.h_deg + 360.0 / (double)g.nsuper;
+  double E = fmin(2.0, (span_dec + span_ra + 2.0 * cell) * (M_PI / 180.0));
+  const double u32 = 5.9604644775390625e-08;  // 2^-24
+  double c = c_r * (1.0 + 4.0 * u32) + 8.0 * u32 * E;
+  double T = c * c * (1.0 + 4.0 * u32);
+  float Tf = (float)T;
+  if ((double)Tf < T) Tf = __uint_as_float(__float_as_uint(Tf) + 1u);  // round up (Tf > 0)
+  R.thr32 = Tf;
+  R.pad_[0] = R.pad_[1] = 0u;
+  out[grp] = R;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+  k_fill_u32<<<blocks, 256, 0, s>>>(p, v, n);
+}
+
+void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64, 0, s>>>(c); }
+
+void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
+                   uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s) {
+  if (n == 0) return;
+  k_keygen<<<cdiv(n, 256), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt);
+}
+
+size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
+size_t sort_block_sums_len(uint32_t n) { return std::max<size_t>(1, cdiv(sort_counts_len(n), SCAN_TILE)); }
+
+void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t n, int key_bits, const SortScratch& sc,
+                hipStream_t s) {
+  if (n <= 1) return;
+  const uint32_t ntiles = cdiv(n, RS_TILE);
+  const uint32_t nc = RS_BINS * ntiles;
+  const uint32_t nsb = cdiv(nc, SCAN_TILE);
+  uint32_t *kin = keys, *vin = vals, *kout = sc.keys_alt, *vout = sc.vals_alt;
+  int passes = (key_bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, n, shift, sc.counts, ntiles);
+    k_scan_reduce<<<nsb, RS_THREADS, 0, s>>>(sc.counts, nc, sc.block_sums);
+    k_scan_top<<<1, RS_THREADS, 0, s>>>(sc.block_sums, nsb);
+    k_scan_down<<<nsb, RS_THREADS, 0, s>>>(sc.counts, sc.counts, nc, sc.block_sums);
+    k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, n, shift, sc.counts, ntiles);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  if (kin != keys) {
+    (void)hipMemcpyAsync(keys, kin, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(vals, vin, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+  }
+}
+
+void launch_zone_tables(const Geom& g, int32_t* zmarg, double2* zone_cs, double2* super_cs,
+                        hipStream_t s) {
+  uint32_t n = std::max<uint32_t>((uint32_t)g.nz, super_cs ? g.nsuper : 0u);
+  k_zone_tables<<<cdiv(n, 256), 256, 0, s>>>(g, zmarg, zone_cs, super_cs);
+}
+
+void launch_zone_starts(const uint32_t* keys, uint32_t n, const Geom& g, uint32_t* zstart,
+                        hipStream_t s) {
+  k_zone_starts<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(keys, n, g, zstart);
+}
+
+void launch_layout64(const uint32_t* vals, uint32_t n, const double* ra, const double* dec,
+                     Rec64* rec, hipStream_t s) {
+  if (n == 0) return;
+  k_layout64<<<cdiv(n, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
+}
+
+void launch_layout32(const uint32_t* keys, const uint32_t* vals, uint32_t n, const double* ra,
+                     const double* dec, const Geom& g, const double2* zone_cs,
+                     const double2* super_cs, Rec32* rec, double2* radec, hipStream_t s) {
+  if (n == 0) return;
+  k_layout32<<<cdiv(n, 256), 256, 0, s>>>(keys, vals, n, ra, dec, g, zone_cs, super_cs, rec, radec);
+}
+
+void launch_merge_lb(const uint32_t* keysA, uint32_t na, const uint32_t* keysB, uint32_t nb,
+                     uint32_t* lb, hipStream_t s) {
+  if (na == 0) return;
+  uint32_t blocks = cdiv((uint64_t)na + nb, MP_TILE);
+  k_merge_lb<<<blocks, MP_THREADS, 0, s>>>(keysA, na, keysB, nb, lb);
+}
+
+void launch_ranges(const uint32_t* keysA, uint32_t na, const uint32_t* lb, const uint32_t* keysB,
+                   uint32_t nb, const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
+                   double c_r, GroupRanges* out, hipStream_t s) {
+  uint32_t ngroups = cdiv(na, GROUP);
+  if (ngroups == 0) return;
+  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, nb, zstartB, zmarg, g, c_r, out,
+                                              ngroups);
+}
+
+}  // namespace hlc

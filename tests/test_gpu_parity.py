@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Every comparison is a bit-exact pair set and |sep_gpu - sep_oracle| <= 1e-9
+arcsec, for both filter precisions.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import assert_same, gpu_xmatch, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [pytest.param(1, id="fp64"), pytest.param(0, id="fp32")]
+
+
+@pytest.fixture(scope="module")
+def hlc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_07331_amd as m
+    m.load()
+    return m
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_patch_100k(hlc, prec):
+    c = synth.patch_pair()
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, prec)
+    n = assert_same(keys, sep, ref, label=f"patch prec={prec}")
+    _print("patch pairs", n, hlc.last_stats())
+
+
+KINDS = ["random", "pole", "seam", "grid", "dup", "same", "dense"]
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("kind", KINDS)
+def test_adversarial(hlc, kind, prec):
+    for seed, r in ((0, 0.5), (1, 2.0), (2, 7.0)):
+        a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 2999, seed, r)
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec)
+        assert_same(keys, sep, ref, label=f"{kind} seed={seed} r={r}")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_zone_heights_and_cells(hlc, prec):
+    """Tuned geometries: thin zones (many halo copies), wide zones, coarse and fine cells."""
+    a_ra, a_dec, b_ra, b_dec = synth.adversarial("dense", 3001, 5, 2.0)
+    pr, pd = synth.polar_caps(synth.rng(77, 0), 3000, 0.05)
+    a_ra, a_dec = np.concatenate([a_ra, pr[:1500]]), np.concatenate([a_dec, pd[:1500]])
+    b_ra, b_dec = np.concatenate([b_ra, pr[1500:]]), np.concatenate([b_dec, pd[1500:]])
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, 2.0)
+    for zh in (4.01, 5.0, 30.0, 700.0, 3600.0 * 4):
+        for cells in (0, 1, 6, 14):
+            tun = {"zone_height_arcsec": zh, "ra_cell_bins_log2": cells}
+            keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec, tuning=tun)
+            assert_same(keys, sep, ref, label=f"zh={zh} cells={cells}")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_ragged_sizes(hlc, prec):
+    g = synth.rng(200, 0)
+    for na, nb in ((1, 1), (1, 50), (15, 16), (16, 17), (17, 15), (63, 65), (64, 64), (4095, 4097),
+                   (100_003, 7), (7, 100_003), (65_537, 65_535)):
+        a_ra, a_dec = synth.uniform_patch(g, na, 10.0, 10.2, -5.0, -4.8)
+        b_ra, b_dec = synth.uniform_patch(g, nb, 10.0, 10.2, -5.0, -4.8)
+        r = 30.0
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec)
+        assert_same(keys, sep, ref, label=f"na={na} nb={nb}")
+
+
+def test_empty_and_invalid(hlc):
+    import torch
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    one_ra = to_dev([10.0])
+    one_dec = to_dev([20.0])
+    out = torch.empty((4, 2), dtype=torch.int32, device="cuda")
+    sep = torch.empty(4, dtype=torch.float64, device="cuda")
+    for prec in (0, 1):
+        st, n = hlc.hlc_xmatch(e, e, one_ra, one_dec, 1.0, out, sep, precision=prec)
+        assert st == hlc.HLC_OK and n == 0
+        st, n = hlc.hlc_xmatch(one_ra, one_dec, e, e, 1.0, out, sep, precision=prec)
+        assert st == hlc.HLC_OK and n == 0
+        st, n = hlc.hlc_xmatch(e, e, e, e, 1.0, out, sep, precision=prec)
+        assert st == hlc.HLC_OK and n == 0
+        # empty side does not hide a bad coordinate on the other
+        st, n = hlc.hlc_xmatch(e, e, to_dev([10.0]), to_dev([91.0]), 1.0, out, sep, precision=prec)
+        assert st == hlc.HLC_E_INVAL
+    bad = [(float("nan"), 0.0), (0.0, float("nan")), (-1e-300, 0.0), (360.0000001, 0.0), (10.0, 90.5),
+           (10.0, -90.0000001), (float("inf"), 0.0)]
+    g = synth.rng(201, 0)
+    ra, dec = synth.uniform_sphere(g, 1000)
+    for prec in (0, 1):
+        for (x, y) in bad:
+            ra2, dec2 = ra.copy(), dec.copy()
+            ra2[517], dec2[517] = x, y
+            st, _ = hlc.hlc_xmatch(to_dev(ra2), to_dev(dec2), to_dev(ra), to_dev(dec), 1.0, out, sep,
+                                   precision=prec)
+            assert st == hlc.HLC_E_INVAL, (x, y)
+            st, _ = hlc.hlc_xmatch(to_dev(ra), to_dev(dec), to_dev(ra2), to_dev(dec2), 1.0, out, sep,
+                                   precision=prec)
+            assert st == hlc.HLC_E_INVAL, (x, y)
+        # the boundary values themselves are valid
+        ra2, dec2 = ra.copy(), dec.copy()
+        ra2[:4] = [0.0, 360.0, 0.0, 360.0]
+        dec2[:4] = [90.0, -90.0, -90.0, 90.0]
+        st, _ = hlc.hlc_xmatch(to_dev(ra2), to_dev(dec2), to_dev(ra), to_dev(dec), 1.0, out, sep,
+                               precision=prec)
+        assert st in (hlc.HLC_OK, hlc.HLC_E_OVERFLOW)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_overflow_reports_required_count(hlc, prec):
+    import torch
+    c = synth.patch_pair(scale=0.2)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    args = [to_dev(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+    for cap in (0, 1, len(ref) - 1):
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+        sep = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+        st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, sep, precision=prec, capacity=cap)
+        assert st == hlc.HLC_E_OVERFLOW and n == len(ref)
+    out = torch.empty((len(ref), 2), dtype=torch.int32, device="cuda")
+    sep = torch.empty(len(ref), dtype=torch.float64, device="cuda")
+    st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, sep, precision=prec)
+    assert st == hlc.HLC_OK and n == len(ref)
+    # HLC_NO_SEP: no separation buffer needed
+    st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, None, precision=prec, flags=hlc.HLC_NO_SEP)
+    assert st == hlc.HLC_OK and n == len(ref)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_threshold_ties_exact(hlc, prec):
+    """B at exactly r (dyadic radius) along meridians, the equator and across a pole, +-k ulp."""
+    g = np.random.default_rng(5)
+    r = 3.515625  # 2^-10 deg
+    rdeg = r / 3600.0
+    A_ra, A_dec, B_ra, B_dec, truth = [], [], [], [], []
+    for _ in range(300):
+        ra = float(g.uniform(0, 360))
+        dec = float(g.uniform(-80, 80))
+        for k in range(-2, 3):
+            dd = dec + rdeg
+            for _ in range(abs(k)):
+                dd = float(np.nextafter(dd, math.inf if k > 0 else -math.inf))
+            A_ra.append(ra); A_dec.append(dec); B_ra.append(ra); B_dec.append(dd)
+            truth.append(abs(Fraction(dd) - Fraction(dec)) <= Fraction(r) / 3600)
+    for _ in range(100):
+        ra = float(g.uniform(0, 360))
+        for k in range(-2, 3):
+            x = ra + rdeg
+            for _ in range(abs(k)):
+                x = float(np.nextafter(x, math.inf if k > 0 else -math.inf))
+            if x >= 360.0:
+                x -= 360.0
+            d = abs(Fraction(x) - Fraction(ra))
+            d = min(d, 360 - d)
+            A_ra.append(ra); A_dec.append(0.0); B_ra.append(x); B_dec.append(0.0)
+            truth.append(d <= Fraction(r) / 3600)
+    # spread the pairs out so each A only meets its own B
+    a_ra, a_dec = np.array(A_ra), np.array(A_dec)
+    b_ra, b_dec = np.array(B_ra), np.array(B_dec)
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+    keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec)
+    assert_same(keys, sep, ref, label="ties")
+    own = set(int(k) for k in keys if (k >> np.uint64(32)) == (k & np.uint64(0xffffffff)))
+    for i, t in enumerate(truth):
+        assert ((i << 32) | i in own) == t, i
+    st = hlc.last_stats()
+    assert st["n_ties"] > 0
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_invariants(hlc, prec):
+    a_ra, a_dec, b_ra, b_dec = (synth.quantize(x) for x in synth.adversarial("seam", 3000, 9, 2.0))
+    a_ra[a_ra >= 360.0] = 0.0
+    b_ra[b_ra >= 360.0] = 0.0
+    base, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec)
+    assert len(base) > 0
+    sw, sep_sw = gpu_xmatch(b_ra, b_dec, a_ra, a_dec, 2.0, prec)
+    t = ((sw & np.uint64(0xffffffff)) << np.uint64(32)) | (sw >> np.uint64(32))
+    order = np.argsort(t)
+    assert np.array_equal(t[order], base)
+    assert np.max(np.abs(sep_sw[order] - sep)) <= 1e-12
+    for shift in (180.0, 2.0 ** -30 * 98765):
+        rot, _ = gpu_xmatch(np.mod(a_ra + shift, 360.0), a_dec, np.mod(b_ra + shift, 360.0), b_dec, 2.0, prec)
+        assert np.array_equal(rot, base)
+    fl, _ = gpu_xmatch(a_ra, -a_dec, b_ra, -b_dec, 2.0, prec)
+    assert np.array_equal(fl, base)
+
+
+def test_precisions_agree_and_deterministic(hlc):
+    c = synth.patch_pair(scale=0.5, seed_sub=3)
+    k64, s64 = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, 1)
+    k32, s32 = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, 0)
+    assert np.array_equal(k64, k32)
+    assert np.max(np.abs(s64 - s32)) <= 1e-9
+    k64b, s64b = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, 1)
+    assert np.array_equal(k64, k64b) and np.array_equal(s64, s64b)
+    k32b, s32b = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, 0)
+    assert np.array_equal(k32, k32b) and np.array_equal(s32, s32b)
+
+
+def test_allocation_failure_injection(hlc):
+    c = synth.patch_pair(scale=0.05)
+    hlc.shutdown()
+    os.environ["HLC_TEST_FAIL_ALLOC"] = "1"
+    try:
+        args = [to_dev(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+        import torch
+        out = torch.empty((10000, 2), dtype=torch.int32, device="cuda")
+        sep = torch.empty(10000, dtype=torch.float64, device="cuda")
+        st, _ = hlc.hlc_xmatch(*args, 1.0, out, sep, precision=1)
+        assert st == hlc.HLC_E_NOMEM
+    finally:
+        del os.environ["HLC_TEST_FAIL_ALLOC"]
+    keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 1.0, 1)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 1.0)
+    assert_same(keys, sep, ref, label="after NOMEM")
+
+
+@pytest.fixture(scope="module")
+def fullsky():
+    return synth.fullsky_pair()
+
+
+@pytest.fixture(scope="module")
+def fullsky_ref(fullsky):
+    c = fullsky
+    return oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_fullsky_10M(hlc, fullsky, fullsky_ref, prec):
+    """The headline workload at full size, every pair compared."""
+    c = fullsky
+    keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, prec)
+    n = assert_same(keys, sep, fullsky_ref, label=f"fullsky prec={prec}")
+    _print("fullsky pairs", n, hlc.last_stats())
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 5.0])
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_stress_2M(hlc, r, prec):
+    """Precision-stress recipe at 2M x 2M (1000 clumps): counterparts on [0.99 r, 1.01 r]."""
+    c = synth.stress_pair(r, n=2_000_000, n_clumps=1000)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, r)
+    keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, r, prec,
+                           tuning={"zone_height_arcsec": 10.0 * r})
+    n = assert_same(keys, sep, ref, label=f"stress r={r}")
+    _print("stress", r, "pairs", n, hlc.last_stats())

@@ -22,7 +22,7 @@
  *     (indistinguishable at double-double precision) count as matches.
  *   - r_arcsec must lie in (0, 3600]; 0 <= na, nb < 2^31.
  *   - A and B may be the same arrays; they are still two catalogues, so
- *     (i, i) is reported with separation 0.
+ *     (i, i) is reported with separation 0, unless HLC_SELF is set.
  *
  * Memory and ownership
  *   - Coordinate and output pointers are DEVICE pointers (hipMalloc'd, or a
@@ -70,6 +70,10 @@ typedef struct {
 #define HLC_NO_SEP 0x1u   /* do not write separations (out_sep may be NULL)    */
 #define HLC_PROFILE 0x2u  /* time each stage with HIP events (hlc_last_stats)  */
 #define HLC_SORTED 0x4u   /* reserved: sorted output is not implemented        */
+#define HLC_SELF 0x8u     /* self-match: B is the same arrays as A; each       *
+                           * unordered pair is reported once as (i, j), i < j, *
+                           * and (i, i) never (the self-match data sets of     *
+                           * section 5, Table 2). One partition serves both.   */
 
 /* Optional fixed tuning; zero fields mean "choose automatically". */
 typedef struct hlc_tuning {
@@ -83,7 +87,7 @@ typedef struct hlc_opts {
   void *stream;              /* hipStream_t; NULL = the null stream            */
   int64_t capacity;          /* length of out_pairs / out_sep, in pairs        */
   int64_t *n_pairs;          /* host pointer; out: pairs found (or required)  */
-  uint32_t flags;            /* HLC_NO_SEP | HLC_PROFILE                       */
+  uint32_t flags;            /* HLC_NO_SEP | HLC_PROFILE | HLC_SELF            */
   const hlc_tuning *tuning;  /* NULL = automatic                               */
 } hlc_opts;
 

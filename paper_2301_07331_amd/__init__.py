@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhlc.so")
 
 HLC_OK, HLC_E_INVAL, HLC_E_NOMEM, HLC_E_OVERFLOW, HLC_E_DEVICE, HLC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 HLC_FP32_RECHECK, HLC_FP64 = 0, 1
-HLC_NO_SEP, HLC_PROFILE, HLC_SORTED = 0x1, 0x2, 0x4
+HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF = 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = ["hlc_xmatch", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
            "hlc_xmatch_stream", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
@@ -171,6 +171,44 @@ def xmatch(a_ra, a_dec, b_ra, b_dec, r_arcsec, *, precision=HLC_FP32_RECHECK, ca
             raise HLCError(st, "hlc_xmatch")
         return pairs[:n], (sep[:n] if want_sep else None)
     raise HLCError(HLC_E_OVERFLOW, "hlc_xmatch")
+
+
+class Part:
+    """A catalogue partitioned on the device (hlc_partition); free with .free()."""
+
+    def __init__(self, handle, n, r_arcsec):
+        self.handle, self.n, self.r_arcsec = handle, n, r_arcsec
+
+    def free(self):
+        if self.handle:
+            load().hlc_part_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hlc_partition(ra, dec, r_arcsec, *, stream=None, tuning=None):
+    """Partition one catalogue for reuse; returns (status, Part or None)."""
+    _check_coords(ra, dec)
+    o, n, tu = make_opts(HLC_FP64, 0, stream, 0, tuning)
+    h = C.c_void_p(0)
+    st = load().hlc_partition(_ptr(ra), _ptr(dec), ra.numel(), float(r_arcsec), C.byref(o), C.byref(h))
+    return st, (Part(h.value, ra.numel(), r_arcsec) if st == HLC_OK else None)
+
+
+def hlc_xmatch_part(A: Part, B: Part, r_arcsec, out_pairs, out_sep, *, precision=HLC_FP32_RECHECK,
+                    capacity=None, stream=None, flags=0):
+    """Cross-match two partitioned catalogues. Returns (status, n_pairs)."""
+    if capacity is None:
+        capacity = 0 if out_pairs is None else out_pairs.shape[0]
+    o, n, tu = make_opts(precision, capacity, stream, flags, None)
+    st = load().hlc_xmatch_part(A.handle, B.handle, float(r_arcsec), _ptr(out_pairs), _ptr(out_sep),
+                                C.byref(o))
+    return st, n.value
 
 
 def last_stats() -> dict:

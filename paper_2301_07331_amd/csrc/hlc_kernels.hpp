@@ -74,6 +74,8 @@ struct MatchArgs {
   double H_lo, H_hi;            // haversine: certain in / candidate (FP64 band)
   // A entries flagged as halo copies are skipped (partition reuse)
   int skip_halo_a;
+  // self-match: A and B are one catalogue; keep pairs with a < b only
+  int self_only;
 };
 
 void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s);

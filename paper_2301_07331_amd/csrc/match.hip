@@ -101,8 +101,9 @@ __device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2
       // entries include halo copies of B sources this A meets in its own
       // zone: only entries of the A source's own zone count
       const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-      in = same_zone && d2 <= a.t_lo64;
-      band = same_zone && !in && d2 <= a.t_hi64;
+      const bool keep = same_zone && (!a.self_only || ia < ib);
+      in = keep && d2 <= a.t_lo64;
+      band = keep && !in && d2 <= a.t_hi64;
       if (in) sep = 2.0 * asin(0.5 * sqrt(d2)) * RAD2ARCSEC;
     }
     emit_pairs(in, ia, ib, sep, o);
@@ -226,8 +227,9 @@ __device__ inline void flush32(const MatchArgs& a, const OutArgs& o, const uint2
       ib = a.recB32[ent.y].idx & IDX_MASK;
       double h = haversine64(pa.x, pa.y, pb.x, pb.y);
       const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-      in = same_zone && h < a.H_lo;
-      band = same_zone && !in && h <= a.H_hi;
+      const bool keep = same_zone && (!a.self_only || ia < ib);
+      in = keep && h < a.H_lo;
+      band = keep && !in && h <= a.H_hi;
       if (in) sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
     }
     emit_pairs(in, ia, ib, sep, o);

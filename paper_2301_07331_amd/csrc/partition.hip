@@ -281,7 +281,7 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double2* __re
         if (2.0 * mm + 1.0 < (double)g.nbins) m = (int32_t)mm;
       }
     }
-    zmarg[z] = m;
+    if (zmarg != nullptr) zmarg[z] = m;
     double mid = fmin(fmax(-90.0 + ((double)z + 0.5) * g.h_deg, -90.0), 90.0);
     double s, c;
     sincos_deg(mid, &s, &c);

@@ -263,3 +263,29 @@ def test_stress_2M(hlc, r, prec):
                            tuning={"zone_height_arcsec": 10.0 * r})
     n = assert_same(keys, sep, ref, label=f"stress r={r}")
     _print("stress", r, "pairs", n, hlc.last_stats())
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_self_match(hlc, prec):
+    """HLC_SELF: each unordered pair once as (i, j), i < j, never (i, i)."""
+    import torch
+    a_ra, a_dec, _, _ = synth.adversarial("dense", 3000, 11, 2.0)
+    c = synth.patch_pair(scale=0.3, seed_sub=5)
+    ra = np.concatenate([a_ra, c.a_ra, c.b_ra])
+    dec = np.concatenate([a_dec, c.a_dec, c.b_dec])
+    full = oracle.xmatch(ra, dec, ra, dec, 1.0)
+    keep = full.a < full.b
+    R = type("R", (), {})()
+    R.keys = lambda: full.keys()[keep]
+    R.sep = full.sep[keep]
+    t_ra, t_dec = to_dev(ra), to_dev(dec)
+    pairs, sep = hlc.xmatch(t_ra, t_dec, t_ra, t_dec, 1.0, precision=prec, flags=hlc.HLC_SELF)
+    p = pairs.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    keys = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+    order = np.argsort(keys)
+    assert_same(keys[order], sep.cpu().numpy()[order], R, label="self")
+    # B must be the same arrays
+    out = torch.empty((4, 2), dtype=torch.int32, device="cuda")
+    s = torch.empty(4, dtype=torch.float64, device="cuda")
+    st, _ = hlc.hlc_xmatch(t_ra, t_dec, t_ra.clone(), t_dec, 1.0, out, s, flags=hlc.HLC_SELF)
+    assert st == hlc.HLC_E_INVAL

@@ -79,7 +79,10 @@ typedef struct {
 typedef struct hlc_tuning {
   double zone_height_arcsec; /* Dec zone height; >= 2.0001 r is enforced       */
   int32_t ra_cell_bins_log2; /* log2 of RA bins per FP32 cell (0 = auto)       */
-  int32_t reserved[6];
+  int32_t reserved0;
+  double zone_height_factor; /* batched form: scale of each job's density-     *
+                              * derived zone height (0 = autotuned and cached)  */
+  int32_t reserved[4];
 } hlc_tuning;
 
 typedef struct hlc_opts {
@@ -133,11 +136,20 @@ int hlc_xmatch_part(const struct hlc_part *A, const struct hlc_part *B, double r
 
 /* Many independent jobs in one call (section 4.3.1's launch geometry applied
  * to thousands of calculation blocks at once). Job j matches
- * A[a_off, a_off+na) against B[b_off, b_off+nb) at radius r_arcsec.
- *   jobs [njobs]: HOST array. a_ra..b_dec: device arrays holding all jobs.
+ * A[a_off, a_off+na) against B[b_off, b_off+nb) at radius r_arcsec; job
+ * ranges may overlap. Each job is partitioned in a local frame derived from
+ * its own sources; all jobs share one sort and one persistent match launch
+ * over a cost-ordered work queue. Repeated calls with the same arguments
+ * replay a captured HIP graph.
+ *   jobs [njobs]: HOST array, 0 <= njobs <= 65536; r_arcsec in (0, 3600].
+ *   a_ra..b_dec: device arrays holding all jobs; the sum of na and the sum
+ *     of nb must each be below 2^30.
  *   out_pairs / out_sep: device, capacity opts->capacity; pair indices are
  *     GLOBAL (into the packed arrays).
  *   job_pair_count [njobs]: device int64, pairs found per job (may be NULL).
+ *   opts->tuning->zone_height_factor: 0 or no tuning = autotuned on first
+ *     use for this batch shape and cached (in memory, and in the JSON file
+ *     named by $HLC_TUNE_CACHE when set).
  * Total pairs go to *opts->n_pairs; overflow behaves as in hlc_xmatch.     */
 typedef struct hlc_job {
   int64_t a_off, na, b_off, nb;

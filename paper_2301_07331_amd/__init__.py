@@ -23,7 +23,8 @@ EXPORTS = ["hlc_xmatch", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "h
 
 class hlc_tuning(C.Structure):
     _fields_ = [("zone_height_arcsec", C.c_double), ("ra_cell_bins_log2", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("reserved0", C.c_int32), ("zone_height_factor", C.c_double),
+                ("reserved", C.c_int32 * 4)]
 
 
 class hlc_opts(C.Structure):
@@ -129,6 +130,7 @@ def make_opts(precision=HLC_FP32_RECHECK, capacity=0, stream=None, flags=0, tuni
         tu = hlc_tuning()
         tu.zone_height_arcsec = float(tuning.get("zone_height_arcsec", 0.0))
         tu.ra_cell_bins_log2 = int(tuning.get("ra_cell_bins_log2", 0))
+        tu.zone_height_factor = float(tuning.get("zone_height_factor", 0.0))
         o.tuning = C.pointer(tu)
     return o, n, tu
 
@@ -208,6 +210,68 @@ def hlc_xmatch_part(A: Part, B: Part, r_arcsec, out_pairs, out_sep, *, precision
     o, n, tu = make_opts(precision, capacity, stream, flags, None)
     st = load().hlc_xmatch_part(A.handle, B.handle, float(r_arcsec), _ptr(out_pairs), _ptr(out_sep),
                                 C.byref(o))
+    return st, n.value
+
+
+def _check_host(*ts):
+    import torch
+    for t in ts:
+        if not (t.device.type == "cpu" and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 1):
+            raise ValueError("streamed coordinates must be contiguous 1-D float64 host tensors (pinned)")
+
+
+def hlc_xmatch_stream(a_ra, a_dec, b_ra, b_dec, r_arcsec, sink, *, precision=HLC_FP32_RECHECK,
+                      ring_pairs=0, stream=None, flags=0):
+    """Stream host catalogues (torch CPU tensors, ideally pinned) through the GPU.
+
+    sink(pairs_ptr, sep_ptr, n) is called from the calling thread with host
+    pointers to n (a, b) uint32 pairs and n FP64 separations (sep_ptr is None
+    with HLC_NO_SEP); it returns 0 to continue. Returns (status, n_pairs).
+    """
+    _check_host(a_ra, a_dec, b_ra, b_dec)
+    o, n, tu = make_opts(precision, ring_pairs, stream, flags, None)
+    cb = SINK(lambda p, s_, k, u: int(sink(p, s_, k) or 0))
+    st = load().hlc_xmatch_stream(_ptr(a_ra), _ptr(a_dec), a_ra.numel(), _ptr(b_ra), _ptr(b_dec),
+                                  b_ra.numel(), float(r_arcsec), cb, None, C.byref(o))
+    return st, n.value
+
+
+def xmatch_stream(a_ra, a_dec, b_ra, b_dec, r_arcsec, **kw):
+    """Collect the streamed result into numpy arrays: (pairs[n, 2] uint32, sep[n] float64)."""
+    import numpy as np
+    parts_p, parts_s = [], []
+
+    def sink(p, s_, k):
+        parts_p.append(np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint32)), shape=(k, 2)).copy())
+        if s_:
+            parts_s.append(np.ctypeslib.as_array(C.cast(s_, C.POINTER(C.c_double)), shape=(k,)).copy())
+        return 0
+
+    st, n = hlc_xmatch_stream(a_ra, a_dec, b_ra, b_dec, r_arcsec, sink, **kw)
+    if st != HLC_OK:
+        raise HLCError(st, "hlc_xmatch_stream")
+    pairs = np.concatenate(parts_p) if parts_p else np.empty((0, 2), np.uint32)
+    sep = np.concatenate(parts_s) if parts_s else np.empty(0)
+    assert len(pairs) == n
+    return pairs, sep
+
+
+def hlc_xmatch_batch(jobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep, job_pair_count=None, *,
+                     precision=HLC_FP32_RECHECK, capacity=None, stream=None, flags=0, tuning=None):
+    """Batched cross-match. jobs: sequence of (a_off, na, b_off, nb, r_arcsec).
+
+    Coordinates are device tensors holding all jobs; job_pair_count is an
+    optional int64 device tensor of len(jobs). Returns (status, n_pairs).
+    """
+    _check_coords(a_ra, a_dec, b_ra, b_dec)
+    arr = (hlc_job * max(1, len(jobs)))()
+    for k, (ao, na, bo, nb, r) in enumerate(jobs):
+        arr[k].a_off, arr[k].na, arr[k].b_off, arr[k].nb, arr[k].r_arcsec = int(ao), int(na), int(bo), int(nb), float(r)
+    if capacity is None:
+        capacity = 0 if out_pairs is None else out_pairs.shape[0]
+    o, n, tu = make_opts(precision, capacity, stream, flags, tuning)
+    st = load().hlc_xmatch_batch(arr, len(jobs), _ptr(a_ra), _ptr(a_dec), _ptr(b_ra), _ptr(b_dec),
+                                 _ptr(out_pairs), _ptr(out_sep), _ptr(job_pair_count), C.byref(o))
     return st, n.value
 
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlc.so")
-SOURCES = ["partition.hip", "match.hip", "api.hip"]
+SOURCES = ["partition.hip", "match.hip", "stream.hip", "batch.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

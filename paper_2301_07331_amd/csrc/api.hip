@@ -14,6 +14,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/hlc.h"
 #include "hlc_kernels.hpp"
@@ -210,7 +213,8 @@ int tuned_cells(const hlc_opts* o) { return o->tuning ? o->tuning->ra_cell_bins_
 
 // One partitioned catalogue.
 struct Side {
-  uint32_t n_src = 0, n = 0;  // sources, entries (halo copies included)
+  uint32_t n_src = 0, n_cap = 0;  // sources; entry capacity (2 n_src with a halo)
+  DevCount cnt{0, 0, nullptr};    // entries, halo copies included (device-side)
   uint32_t *keys = nullptr, *vals = nullptr;
   Rec64* r64 = nullptr;
   Rec32* r32 = nullptr;
@@ -223,9 +227,8 @@ struct Tables {
   double2* super_cs = nullptr;
 };
 
-// keygen -> sort -> layout for one catalogue. `cap` entries are available in
-// the side's buffers (n, or 2n with a halo). With a halo, the halo count is
-// read back (one synchronisation) before sorting.
+// keygen -> sort -> layout for one catalogue. The side's buffers hold n
+// entries, or 2n with a halo; the halo count stays on the device (DevCount).
 // Profiling event slots (HLC_PROFILE): per partition, {after keygen,
 // before sort, after sort, after layout}; -1 = not recorded.
 struct Slots {
@@ -244,19 +247,13 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
   sd.dec = dec;
   launch_keygen(ra, dec, n, g, halo, err_bit, sd.keys, sd.vals, dev.cnt, s);
   mark(dev, sl.keygen, s);
-  uint32_t nent = n;
-  if (halo) {
-    HLC_TRY(hipMemcpyAsync(dev.cnt_host, dev.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HLC_TRY(hipStreamSynchronize(s));
-    if (dev.cnt_host->err) return HLC_E_INVAL;
-    nent = n + (uint32_t)dev.cnt_host->n_halo;
-  }
-  sd.n = nent;
+  sd.n_cap = halo ? 2 * n : n;
+  sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
   mark(dev, sl.sort_begin, s);
-  radix_sort(sd.keys, sd.vals, nent, key_bits(g), sc, s);
+  radix_sort(sd.keys, sd.vals, sd.cnt, key_bits(g), sc, s);
   mark(dev, sl.sort, s);
-  if (l64) launch_layout64(sd.vals, nent, ra, dec, sd.r64, s);
-  if (l32) launch_layout32(sd.keys, sd.vals, nent, ra, dec, g, tb.zone_cs, tb.super_cs, sd.r32, sd.radec, s);
+  if (l64) launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
+  if (l32) launch_layout32(sd.keys, sd.vals, sd.cnt, ra, dec, g, tb.zone_cs, tb.super_cs, sd.r32, sd.radec, s);
   mark(dev, sl.layout, s);
   return HLC_OK;
 }
@@ -281,16 +278,15 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   launch_zone_tables(g, w.zmarg, tb.zone_cs, nullptr, s);
   const uint32_t* zstart = w.zstartB;
   if (!zstart) {
-    launch_zone_starts(B.keys, B.n, g, w.zstart_buf, s);
+    launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, s);
     zstart = w.zstart_buf;
   }
-  launch_merge_lb(A.keys, A.n, B.keys, B.n, w.lb, s);
-  launch_ranges(A.keys, A.n, w.lb, B.keys, B.n, zstart, w.zmarg, g, th.c_r, w.ranges, s);
+  launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, w.lb, s);
+  launch_ranges(A.keys, A.cnt, w.lb, B.keys, zstart, w.zmarg, g, th.c_r, w.ranges, s);
   if (prof) (void)hipEventRecord(dev.ev[8], s);
   MatchArgs ma{};
   ma.ranges = w.ranges;
-  ma.na = A.n;
-  ma.nb = B.n;
+  ma.na = A.cnt;
   ma.recA64 = A.r64;
   ma.recB64 = B.r64;
   ma.t_lo64 = th.t_lo64;
@@ -462,10 +458,25 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     *band_needed = h.n_band;
     return HLC_OK;
   }
-  fill_stats(h, na, nb, B.n, g);
+  fill_stats(h, na, nb, nb + (int64_t)h.n_halo, g);
   if (prof) fill_times(*dev, true);
   *o->n_pairs = (int64_t)h.n_pairs;
   return h.n_pairs > (unsigned long long)o->capacity ? HLC_E_OVERFLOW : HLC_OK;
+}
+
+// xmatch_impl with the band-list retry.
+int xmatch_core(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
+                const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
+                double* out_sep, const hlc_opts* o) {
+  uint64_t band_cap = (1u << 20) + (uint64_t)(na + nb) / 64;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    uint64_t need = 0;
+    int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, band_cap,
+                         &need);
+    if (need == 0) return st;
+    band_cap = need + need / 4 + 1024;
+  }
+  return HLC_E_NOMEM;
 }
 
 int validate_only(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
@@ -521,15 +532,7 @@ int hlc_xmatch(const double* a_ra, const double* a_dec, int64_t na, const double
   if ((opts->flags & HLC_SELF) && (a_ra != b_ra || a_dec != b_dec || na != nb)) return HLC_E_INVAL;
   try {
     if (na == 0 || nb == 0) return validate_only(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, opts);
-    uint64_t band_cap = (1u << 20) + (uint64_t)(na + nb) / 64;
-    for (int attempt = 0; attempt < 3; ++attempt) {
-      uint64_t need = 0;
-      st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep_arcsec, opts,
-                       band_cap, &need);
-      if (need == 0) return st;
-      band_cap = need + need / 4 + 1024;
-    }
-    return HLC_E_NOMEM;
+    return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep_arcsec, opts);
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {
@@ -595,10 +598,15 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     launch_zone_tables(p->g, nullptr, p->tb.zone_cs, p->tb.super_cs, s);
     st = partition(*dev, p->ra, p->dec, nn, p->g, true, true, true, p->tb, sc, 1u, p->side, NO_SLOTS, s);
     if (st == HLC_OK) {
-      launch_zone_starts(p->side.keys, p->side.n, p->g, p->zstart, s);
+      launch_zone_starts(p->side.keys, p->side.cnt, p->g, p->zstart, s);
       st = read_counters(*dev, s, false);
     }
     if (st == HLC_OK && dev->cnt_host->err) st = HLC_E_INVAL;
+    if (st == HLC_OK) {
+      // the entry count is final: keep it on the host side of the part
+      const uint32_t ne = nn + (uint32_t)dev->cnt_host->n_halo;
+      p->side.cnt = DevCount{ne, ne, nullptr};
+    }
     if (st != HLC_OK) {
       hlc_part_free(p);
       return st;
@@ -645,14 +653,14 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       std::memset(&g_stats, 0, sizeof(g_stats));
       return HLC_OK;
     }
-    uint64_t band_cap = (1u << 20) + (uint64_t)(A->side.n + B->side.n) / 64;
+    uint64_t band_cap = (1u << 20) + (uint64_t)(A->side.cnt.cap + B->side.cnt.cap) / 64;
     for (int attempt = 0; attempt < 3; ++attempt) {
       MatchWs w;
       Carve sizing{nullptr};
-      carve_match_ws(sizing, w, A->side.n, g, band_cap, false);
+      carve_match_ws(sizing, w, A->side.cnt.cap, g, band_cap, false);
       HLC_CHECK(ensure_ws(*dev, sizing.off + 256));
       Carve c{(char*)dev->ws};
-      carve_match_ws(c, w, A->side.n, g, band_cap, false);
+      carve_match_ws(c, w, A->side.cnt.cap, g, band_cap, false);
       w.zstartB = B->zstart;
       if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
       launch_zero_counters(dev->cnt, s);
@@ -664,7 +672,7 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
         band_cap = h.n_band + h.n_band / 4 + 1024;
         continue;
       }
-      fill_stats(h, A->side.n_src, B->side.n_src, B->side.n, g);
+      fill_stats(h, A->side.n_src, B->side.n_src, B->side.cnt.cap, g);
       if (prof) fill_times(*dev, false);
       *opts->n_pairs = (int64_t)h.n_pairs;
       return h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK;
@@ -677,14 +685,696 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
   }
 }
 
-int hlc_xmatch_batch(const hlc_job*, int32_t, const double*, const double*, const double*,
-                     const double*, hlc_pair*, double*, int64_t*, const hlc_opts*) {
-  return HLC_E_UNSUPPORTED;
+}  // extern "C"
+
+namespace hlc {
+namespace {
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  int32_t njobs = 0, lb_bits = 31;
+  uint64_t NA = 0, NB = 0;
+  uint32_t ztotal = 0;
+  std::vector<BatchJob> jobs;
+  std::vector<BatchTile> tA, tB;
+};
+
+uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
 }
 
-int hlc_xmatch_stream(const double*, const double*, int64_t, const double*, const double*, int64_t,
-                      double, hlc_sink, void*, const hlc_opts*) {
-  return HLC_E_UNSUPPORTED;
+int build_plan(const hlc_job* jobs, int32_t njobs, BatchPlan& P) {
+  if (njobs < 0 || njobs > 65536) return HLC_E_INVAL;
+  if (njobs > 0 && !jobs) return HLC_E_INVAL;
+  P.njobs = njobs;
+  P.lb_bits = 32 - std::max(1, ceil_log2((uint64_t)std::max(njobs, 1)));
+  P.jobs.resize(njobs);
+  uint64_t ea = 0, eb = 0, zo = 0;
+  const uint32_t zmax = 1u << (P.lb_bits - 8);
+  for (int32_t j = 0; j < njobs; ++j) {
+    const hlc_job& J = jobs[j];
+    if (J.a_off < 0 || J.na < 0 || J.b_off < 0 || J.nb < 0) return HLC_E_INVAL;
+    if (!(J.r_arcsec > 0.0) || !(J.r_arcsec <= 3600.0)) return HLC_E_INVAL;
+    if (J.a_off + J.na >= (int64_t(1) << 31) || J.b_off + J.nb >= (int64_t(1) << 31)) return HLC_E_INVAL;
+    BatchJob& B = P.jobs[j];
+    B.a_off = J.a_off;
+    B.na = J.na;
+    B.b_off = J.b_off;
+    B.nb = J.nb;
+    B.r_arcsec = J.r_arcsec;
+    const double sh = std::sin(0.5 * (J.r_arcsec / 3600.0) * (M_PI / 180.0));
+    B.H_lo = sh * sh * (1.0 - EPS_BAND);
+    B.H_hi = sh * sh * (1.0 + EPS_BAND);
+    B.a_entry = (uint32_t)ea;
+    B.b_entry = (uint32_t)eb;
+    // zone budget: enough zones for about 16 sources per zone row, at most 2^(LB-8)
+    B.zcap = (uint32_t)std::min<uint64_t>(zmax, 4 + (uint64_t)(J.na + J.nb) / 16);
+    B.zoff = (uint32_t)zo;
+    zo += B.zcap + 1;
+    for (int64_t t = 0; t < J.na; t += 256)
+      P.tA.push_back({(uint32_t)j, (uint32_t)(ea + t), (uint32_t)(J.a_off + t),
+                      (uint32_t)std::min<int64_t>(256, J.na - t)});
+    for (int64_t t = 0; t < J.nb; t += 256)
+      P.tB.push_back({(uint32_t)j, (uint32_t)(eb + t), (uint32_t)(J.b_off + t),
+                      (uint32_t)std::min<int64_t>(256, J.nb - t)});
+    ea += J.na;
+    eb += J.nb;
+    if (ea >= (uint64_t(1) << 30) || eb >= (uint64_t(1) << 30) || zo >= (uint64_t(1) << 31))
+      return HLC_E_INVAL;
+  }
+  P.NA = ea;
+  P.NB = eb;
+  P.ztotal = (uint32_t)zo;
+  return HLC_OK;
+}
+
+struct BatchState {  // per device
+  void* tables = nullptr;
+  size_t tables_bytes = 0;
+  uint64_t tables_hash = 0;
+  BatchJob* d_jobs = nullptr;
+  BatchTile *d_tA = nullptr, *d_tB = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  uint64_t graph_key = 0;
+  int ncu = 256;
+};
+BatchState g_bstate[MAX_DEVICES];
+std::vector<std::pair<std::string, double>> g_tune;
+bool g_tune_loaded = false;
+
+void drop_graph(BatchState& B) {
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  B.graph_key = 0;
+}
+
+// Flat {"key": number, ...} JSON cache of tuned factors ($HLC_TUNE_CACHE).
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("HLC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  std::fclose(f);
+  size_t i = 0;
+  while (true) {
+    size_t a = txt.find('"', i);
+    if (a == std::string::npos) break;
+    size_t b = txt.find('"', a + 1);
+    if (b == std::string::npos) break;
+    size_t c = txt.find(':', b);
+    if (c == std::string::npos) break;
+    double v = std::strtod(txt.c_str() + c + 1, nullptr);
+    if (v > 0) g_tune.emplace_back(txt.substr(a + 1, b - a - 1), v);
+    i = c + 1;
+  }
+}
+
+void tune_save() {
+  const char* path = std::getenv("HLC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t k = 0; k < g_tune.size(); ++k)
+    std::fprintf(f, "  \"%s\": %.6g%s\n", g_tune[k].first.c_str(), g_tune[k].second,
+                 k + 1 < g_tune.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+struct BatchBufs {
+  unsigned long long* bounds;
+  JobGeom* geo;
+  uint32_t *kA, *vA, *kB, *vB, *lb, *zstart, *ckey, *cval;
+  int32_t* zmarg;
+  GroupRanges* ranges;
+  Rec64 *rA64, *rB64;
+  Rec32 *rA32, *rB32;
+  double2 *radecA, *radecB;
+  uint2* band;
+  uint32_t* band_job;
+  unsigned long long* jcount;
+  SortScratch sc;
+};
+
+void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, uint64_t band_cap, bool own_jcount) {
+  const uint32_t NA = std::max<uint32_t>((uint32_t)P.NA, 1), NB2 = std::max<uint32_t>(2 * (uint32_t)P.NB, 1);
+  const uint32_t ng = (NA + GROUP - 1) / GROUP;
+  b.bounds = c.take<unsigned long long>(4 * (size_t)std::max(P.njobs, 1));
+  b.geo = c.take<JobGeom>(std::max(P.njobs, 1));
+  b.kA = c.take<uint32_t>(NA);
+  b.vA = c.take<uint32_t>(NA);
+  b.kB = c.take<uint32_t>(NB2);
+  b.vB = c.take<uint32_t>(NB2);
+  carve_sort(c, b.sc, std::max(std::max(NA, NB2), ng));
+  if (fp32) {
+    b.rA32 = c.take<Rec32>(NA);
+    b.rB32 = c.take<Rec32>(NB2);
+    b.radecA = c.take<double2>(NA);
+    b.radecB = c.take<double2>(NB2);
+    b.rA64 = b.rB64 = nullptr;
+  } else {
+    b.rA64 = c.take<Rec64>(NA);
+    b.rB64 = c.take<Rec64>(NB2);
+    b.rA32 = b.rB32 = nullptr;
+    b.radecA = b.radecB = nullptr;
+  }
+  b.lb = c.take<uint32_t>(NA);
+  b.ranges = c.take<GroupRanges>(ng);
+  b.ckey = c.take<uint32_t>(ng);
+  b.cval = c.take<uint32_t>(ng);
+  b.zmarg = c.take<int32_t>(std::max<uint32_t>(P.ztotal, 1));
+  b.zstart = c.take<uint32_t>(std::max<uint32_t>(P.ztotal, 1));
+  b.band = c.take<uint2>(band_cap);
+  b.band_job = c.take<uint32_t>(band_cap);
+  b.jcount = own_jcount ? c.take<unsigned long long>(std::max(P.njobs, 1)) : nullptr;
+}
+
+// Every launch of one batched call, in order, on stream s (no host
+// synchronisation, so the sequence can be captured into a graph).
+void batch_enqueue(Device& dev, BatchState& BS, const BatchPlan& P, const BatchBufs& b, const double* a_ra,
+                   const double* a_dec, const double* b_ra, const double* b_dec, hlc_pair* out_pairs,
+                   double* out_sep, uint64_t cap, unsigned long long* jcount, double factor, bool fp32,
+                   uint64_t band_cap, hipStream_t s) {
+  const uint32_t NA = (uint32_t)P.NA, NB = (uint32_t)P.NB;
+  launch_zero_counters(dev.cnt, s);
+  launch_zero_u64(jcount, (uint32_t)P.njobs, s);
+  launch_job_bounds_init(b.bounds, P.njobs, s);
+  launch_job_bounds(BS.d_tA, (uint32_t)P.tA.size(), BS.d_jobs, a_ra, b_ra, a_ra, a_dec, false, b.bounds,
+                    dev.cnt, s);
+  launch_job_bounds(BS.d_tB, (uint32_t)P.tB.size(), BS.d_jobs, a_ra, b_ra, b_ra, b_dec, true, b.bounds,
+                    dev.cnt, s);
+  launch_job_frames(BS.d_jobs, P.njobs, a_ra, b_ra, b.bounds, P.lb_bits, factor, b.geo, s);
+  launch_batch_keygen(BS.d_tA, (uint32_t)P.tA.size(), b.geo, a_ra, a_dec, P.lb_bits, false, NA, b.kA, b.vA,
+                      dev.cnt, s);
+  launch_batch_keygen(BS.d_tB, (uint32_t)P.tB.size(), b.geo, b_ra, b_dec, P.lb_bits, true, NB, b.kB, b.vB,
+                      dev.cnt, s);
+  const DevCount cA{NA, NA, nullptr};
+  const DevCount cB{NB, 2 * NB, &dev.cnt->n_halo};
+  radix_sort(b.kA, b.vA, cA, 32, b.sc, s);
+  radix_sort(b.kB, b.vB, cB, 32, b.sc, s);
+  if (fp32) {
+    launch_batch_layout32(b.kA, b.vA, cA, a_ra, a_dec, b.geo, P.lb_bits, b.rA32, b.radecA, s);
+    launch_batch_layout32(b.kB, b.vB, cB, b_ra, b_dec, b.geo, P.lb_bits, b.rB32, b.radecB, s);
+  } else {
+    launch_layout64(b.vA, cA, a_ra, a_dec, b.rA64, s);
+    launch_layout64(b.vB, cB, b_ra, b_dec, b.rB64, s);
+  }
+  launch_batch_zone_tables(b.geo, P.njobs, BS.d_jobs, P.ztotal, P.lb_bits, b.kB, cB, b.zmarg, b.zstart, s);
+  launch_merge_lb(b.kA, cA, b.kB, cB, b.lb, s);
+  launch_batch_ranges(b.kA, cA, b.lb, b.kB, b.geo, P.lb_bits, b.zmarg, b.zstart, b.ranges, b.ckey, b.cval, s);
+  const uint32_t ng = (NA + GROUP - 1) / GROUP;
+  radix_sort(b.ckey, b.cval, DevCount{ng, ng, nullptr}, 32, b.sc, s);
+  BatchMatchArgs ma{};
+  ma.ranges = b.ranges;
+  ma.order = b.cval;
+  ma.queue = &dev.cnt->queue;
+  ma.na = cA;
+  ma.keysA = b.kA;
+  ma.keysB = b.kB;
+  ma.recA64 = b.rA64;
+  ma.recB64 = b.rB64;
+  ma.recA32 = b.rA32;
+  ma.recB32 = b.rB32;
+  ma.radecA = b.radecA;
+  ma.radecB = b.radecB;
+  ma.geo = b.geo;
+  ma.lb_bits = P.lb_bits;
+  ma.job_count = jcount;
+  OutArgs oa{};
+  oa.pairs = reinterpret_cast<uint2*>(out_pairs);
+  oa.sep = out_sep;
+  oa.cap = cap;
+  oa.band = b.band;
+  oa.band_job = b.band_job;
+  oa.band_cap = band_cap;
+  oa.cnt = dev.cnt;
+  // persistent grid: four 256-thread blocks per CU (the LDS queue allows four)
+  const uint32_t nblocks = std::max<uint32_t>(1, std::min<uint32_t>(4u * (uint32_t)BS.ncu, (ng + 15) / 16));
+  launch_batch_match(ma, oa, fp32, nblocks, s);
+  launch_batch_certify(a_ra, a_dec, b_ra, b_dec, BS.d_jobs, oa, jcount, s);
+}
+
+int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const double* a_dec,
+               const double* b_ra, const double* b_dec, hlc_pair* out_pairs, double* out_sep,
+               int64_t* job_pair_count, const hlc_opts* o) {
+  BatchPlan P;
+  HLC_CHECK(build_plan(jobs, njobs, P));
+  if ((P.NA > 0 && (!a_ra || !a_dec)) || (P.NB > 0 && (!b_ra || !b_dec))) return HLC_E_INVAL;
+  std::memset(&g_stats, 0, sizeof(g_stats));
+  if (P.NA == 0 || P.NB == 0) {
+    // nothing can match; still reject invalid coordinates
+    int dev_id = 0;
+    Device* dev = nullptr;
+    HLC_CHECK(get_device(&dev, &dev_id));
+    if (job_pair_count && njobs > 0)
+      HLC_TRY(hipMemsetAsync(job_pair_count, 0, sizeof(int64_t) * njobs, (hipStream_t)o->stream));
+    for (const hlc_job* J = jobs; J < jobs + njobs; ++J) {
+      if (J->na > 0) HLC_CHECK(validate_only(a_ra + J->a_off, a_dec + J->a_off, J->na, nullptr, nullptr, 0, J->r_arcsec, o));
+      if (J->nb > 0) HLC_CHECK(validate_only(nullptr, nullptr, 0, b_ra + J->b_off, b_dec + J->b_off, J->nb, J->r_arcsec, o));
+    }
+    *o->n_pairs = 0;
+    return HLC_OK;
+  }
+  int dev_id = 0;
+  Device* dev = nullptr;
+  HLC_CHECK(get_device(&dev, &dev_id));
+  BatchState& BS = g_bstate[dev_id];
+  if (!BS.st) {
+    HLC_TRY(hipStreamCreate(&BS.st));
+    HLC_TRY(hipEventCreateWithFlags(&BS.ev_in, hipEventDisableTiming));
+    HLC_TRY(hipEventCreateWithFlags(&BS.ev_out, hipEventDisableTiming));
+    HLC_TRY(hipEventCreate(&BS.ev_t0));
+    HLC_TRY(hipEventCreate(&BS.ev_t1));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev_id) == hipSuccess && prop.multiProcessorCount > 0)
+      BS.ncu = prop.multiProcessorCount;
+  }
+  hipStream_t us = (hipStream_t)o->stream;
+  HLC_TRY(hipEventRecord(BS.ev_in, us));
+  HLC_TRY(hipStreamWaitEvent(BS.st, BS.ev_in, 0));
+  hipStream_t s = BS.st;
+  const bool fp32 = o->precision == HLC_FP32_RECHECK;
+
+  // device copies of the job and tile tables (kept while the batch repeats)
+  uint64_t th = fnv(P.jobs.data(), P.jobs.size() * sizeof(BatchJob));
+  th = fnv(P.tA.data(), P.tA.size() * sizeof(BatchTile), th);
+  th = fnv(P.tB.data(), P.tB.size() * sizeof(BatchTile), th);
+  if (th != BS.tables_hash || !BS.tables) {
+    drop_graph(BS);
+    Carve sz{nullptr};
+    sz.take<BatchJob>(P.jobs.size());
+    sz.take<BatchTile>(std::max<size_t>(P.tA.size(), 1));
+    sz.take<BatchTile>(std::max<size_t>(P.tB.size(), 1));
+    if (sz.off + 256 > BS.tables_bytes) {
+      if (BS.tables) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(BS.tables);
+        BS.tables = nullptr;
+        BS.tables_bytes = 0;
+      }
+      HLC_CHECK(dev_alloc(&BS.tables, sz.off + 256));
+      BS.tables_bytes = sz.off + 256;
+    }
+    Carve c{(char*)BS.tables};
+    BS.d_jobs = c.take<BatchJob>(P.jobs.size());
+    BS.d_tA = c.take<BatchTile>(std::max<size_t>(P.tA.size(), 1));
+    BS.d_tB = c.take<BatchTile>(std::max<size_t>(P.tB.size(), 1));
+    HLC_TRY(hipMemcpyAsync(BS.d_jobs, P.jobs.data(), P.jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, s));
+    HLC_TRY(hipMemcpyAsync(BS.d_tA, P.tA.data(), P.tA.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
+    HLC_TRY(hipMemcpyAsync(BS.d_tB, P.tB.data(), P.tB.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
+    HLC_TRY(hipStreamSynchronize(s));
+    BS.tables_hash = th;
+  }
+
+  uint64_t band_cap = (1u << 20) + (P.NA + P.NB) / 64;
+  unsigned long long* jcount = reinterpret_cast<unsigned long long*>(job_pair_count);
+  const uint64_t cap = (uint64_t)o->capacity;
+  double* sep = (o->flags & HLC_NO_SEP) ? nullptr : out_sep;
+
+  // zone-height factor: given, cached, or tuned now (eager timed runs)
+  double factor = (o->tuning && o->tuning->zone_height_factor > 0) ? o->tuning->zone_height_factor : 0.0;
+  char bucket[128];
+  std::snprintf(bucket, sizeof bucket, "batch|%s|j%d|a%d|b%d", fp32 ? "fp32" : "fp64",
+                ceil_log2((uint64_t)njobs), ceil_log2(P.NA), ceil_log2(P.NB));
+  if (!(factor > 0)) {
+    tune_load();
+    for (auto& kv : g_tune)
+      if (kv.first == bucket) factor = kv.second;
+  }
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    BatchBufs b;
+    Carve sz{nullptr};
+    carve_batch(sz, b, P, fp32, band_cap, jcount == nullptr);
+    HLC_CHECK(ensure_ws(*dev, sz.off + 256));
+    Carve c{(char*)dev->ws};
+    carve_batch(c, b, P, fp32, band_cap, jcount == nullptr);
+    unsigned long long* jc = jcount ? jcount : b.jcount;
+    if (!(factor > 0)) {
+      // autotune: time each candidate on this batch
+      drop_graph(BS);
+      double best_t = 1e30, best_f = 1.0;
+      for (double f : {0.35, 0.7, 1.4, 2.8}) {
+        HLC_TRY(hipEventRecord(BS.ev_t0, s));
+        batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, f, fp32, band_cap, s);
+        HLC_TRY(hipEventRecord(BS.ev_t1, s));
+        HLC_TRY(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HLC_TRY(hipEventElapsedTime(&ms, BS.ev_t0, BS.ev_t1));
+        if (ms < best_t) { best_t = ms; best_f = f; }
+      }
+      factor = best_f;
+      g_tune.emplace_back(bucket, factor);
+      tune_save();
+    }
+    const bool prof = (o->flags & HLC_PROFILE) != 0;
+    uint64_t gk = fnv(&th, sizeof th);
+    const void* keyp[] = {a_ra, a_dec, b_ra, b_dec, out_pairs, sep, jc, dev->ws, dev->cnt};
+    gk = fnv(keyp, sizeof keyp, gk);
+    const double keyd[] = {factor, (double)cap, (double)band_cap, (double)fp32, (double)dev->ws_bytes};
+    gk = fnv(keyd, sizeof keyd, gk);
+    if (BS.exec == nullptr || BS.graph_key != gk) {
+      drop_graph(BS);
+      HLC_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, factor, fp32, band_cap, s);
+      hipError_t e = hipStreamEndCapture(s, &BS.graph);
+      if (e != hipSuccess) {
+        BS.graph = nullptr;
+        return map_err(e);
+      }
+      e = hipGraphInstantiate(&BS.exec, BS.graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        drop_graph(BS);
+        return map_err(e);
+      }
+      BS.graph_key = gk;
+    }
+    if (prof) HLC_TRY(hipEventRecord(BS.ev_t0, s));
+    HLC_TRY(hipGraphLaunch(BS.exec, s));
+    if (prof) HLC_TRY(hipEventRecord(BS.ev_t1, s));
+    HLC_TRY(hipMemcpyAsync(dev->cnt_host, dev->cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HLC_TRY(hipStreamSynchronize(s));
+    HLC_TRY(hipEventRecord(BS.ev_out, s));
+    HLC_TRY(hipStreamWaitEvent(us, BS.ev_out, 0));
+    const Counters& h = *dev->cnt_host;
+    if (h.err) {
+      *o->n_pairs = 0;
+      return HLC_E_INVAL;
+    }
+    if (h.n_band > band_cap) {
+      band_cap = h.n_band + h.n_band / 4 + 1024;
+      drop_graph(BS);
+      continue;
+    }
+    g_stats.na = (int64_t)P.NA;
+    g_stats.nb = (int64_t)P.NB;
+    g_stats.nb_halo = (int64_t)(P.NB + h.n_halo);
+    g_stats.n_pairs = (int64_t)h.n_pairs;
+    g_stats.n_candidates = (int64_t)h.n_cand;
+    g_stats.n_band = (int64_t)h.n_band;
+    g_stats.n_ties = (int64_t)h.n_ties;
+    g_stats.n_zones = (int32_t)P.ztotal;
+    g_stats.zone_height_arcsec = factor;  // batched form: the zone-height factor used
+    if (prof) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, BS.ev_t0, BS.ev_t1);
+      g_stats.t_total_ms = ms;
+    }
+    *o->n_pairs = (int64_t)h.n_pairs;
+    return h.n_pairs > cap ? HLC_E_OVERFLOW : HLC_OK;
+  }
+  return HLC_E_NOMEM;
+}
+
+}  // namespace
+}  // namespace hlc
+
+extern "C" {
+
+int hlc_xmatch_batch(const hlc_job* jobs, int32_t njobs, const double* a_ra, const double* a_dec,
+                     const double* b_ra, const double* b_dec, hlc_pair* out_pairs, double* out_sep_arcsec,
+                     int64_t* job_pair_count, const hlc_opts* opts) {
+  HLC_CHECK(check_opts(opts));
+  if (opts->flags & HLC_SELF) return HLC_E_UNSUPPORTED;
+  if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
+    return HLC_E_INVAL;
+  try {
+    return batch_impl(jobs, njobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep_arcsec, job_pair_count, opts);
+  } catch (const std::bad_alloc&) {
+    return HLC_E_NOMEM;
+  } catch (...) {
+    return HLC_E_DEVICE;
+  }
+}
+
+}  // extern "C"
+
+namespace hlc {
+namespace {
+
+// Resources of one streaming call, released in one place.
+struct StreamCall {
+  std::vector<void*> dev;
+  std::vector<void*> host;
+  hipStream_t s_copy = nullptr, s_d2h = nullptr;
+  hipEvent_t ev_copy = nullptr, ev_done = nullptr, ev_d2h[2] = {nullptr, nullptr};
+  ~StreamCall() {
+    if (s_copy) (void)hipStreamSynchronize(s_copy);
+    if (s_d2h) (void)hipStreamSynchronize(s_d2h);
+    (void)hipDeviceSynchronize();
+    for (void* p : dev) (void)hipFree(p);
+    for (void* p : host) (void)hipHostFree(p);
+    for (hipEvent_t e : {ev_copy, ev_done, ev_d2h[0], ev_d2h[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (s_copy) (void)hipStreamDestroy(s_copy);
+    if (s_d2h) (void)hipStreamDestroy(s_d2h);
+  }
+  template <class T>
+  int alloc(T** p, size_t n) {
+    void* q = nullptr;
+    HLC_CHECK(dev_alloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+    dev.push_back(q);
+    *p = (T*)q;
+    return HLC_OK;
+  }
+  template <class T>
+  int alloc_host(T** p, size_t n) {
+    void* q = nullptr;
+    if (alloc_fails(n * sizeof(T))) return HLC_E_NOMEM;
+    HLC_TRY(hipHostMalloc(&q, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
+    host.push_back(q);
+    *p = (T*)q;
+    return HLC_OK;
+  }
+};
+
+constexpr int32_t STREAM_DEC_BINS = 8192;
+constexpr int64_t STREAM_SLAB = int64_t(1) << 25;  // sources per host->device copy
+
+int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const double* b_ra_h,
+                const double* b_dec_h, int64_t nb, double r_arcsec, hlc_sink sink, void* user,
+                const hlc_opts* o) {
+  Device* dev = nullptr;
+  HLC_CHECK(get_device(&dev));
+  hipStream_t s = (hipStream_t)o->stream;
+  StreamCall sc;
+  HLC_TRY(hipStreamCreate(&sc.s_copy));
+  HLC_TRY(hipStreamCreate(&sc.s_d2h));
+  HLC_TRY(hipEventCreateWithFlags(&sc.ev_copy, hipEventDisableTiming));
+  HLC_TRY(hipEventCreateWithFlags(&sc.ev_done, hipEventDisableTiming));
+  for (auto& e : sc.ev_d2h) HLC_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+  // ring: two halves, each drained to its own pinned host staging area
+  const int64_t ring = o->capacity > 0 ? o->capacity : (int64_t(1) << 25);
+  const int64_t half = std::max<int64_t>(ring / 2, 1024);
+  hlc_pair* d_pairs;
+  double* d_sep;
+  HLC_CHECK(sc.alloc(&d_pairs, 2 * half));
+  HLC_CHECK(sc.alloc(&d_sep, 2 * half));
+  hlc_pair* h_pairs[2];
+  double* h_sep[2];
+  for (int k = 0; k < 2; ++k) {
+    HLC_CHECK(sc.alloc_host(&h_pairs[k], half));
+    HLC_CHECK(sc.alloc_host(&h_sep[k], half));
+  }
+
+  // 1. copy both catalogues in slabs; a Dec histogram of each slab runs on
+  //    the compute stream while the next slab is in flight
+  double *A_ra, *A_dec, *B_ra, *B_dec;
+  HLC_CHECK(sc.alloc(&A_ra, na));
+  HLC_CHECK(sc.alloc(&A_dec, na));
+  HLC_CHECK(sc.alloc(&B_ra, nb));
+  HLC_CHECK(sc.alloc(&B_dec, nb));
+  uint32_t* hist;
+  HLC_CHECK(sc.alloc(&hist, 2 * STREAM_DEC_BINS));
+  HLC_TRY(hipMemsetAsync(hist, 0, 2 * STREAM_DEC_BINS * sizeof(uint32_t), s));
+  launch_zero_counters(dev->cnt, s);
+  HLC_TRY(hipStreamSynchronize(s));
+  struct Src {
+    const double *ra_h, *dec_h;
+    double *ra, *dec;
+    int64_t n;
+    uint32_t* hist;
+    uint32_t err;
+  } srcs[2] = {{a_ra_h, a_dec_h, A_ra, A_dec, na, hist, 1u},
+               {b_ra_h, b_dec_h, B_ra, B_dec, nb, hist + STREAM_DEC_BINS, 2u}};
+  for (const Src& x : srcs) {
+    for (int64_t off = 0; off < x.n; off += STREAM_SLAB) {
+      const int64_t m = std::min(STREAM_SLAB, x.n - off);
+      HLC_TRY(hipMemcpyAsync(x.ra + off, x.ra_h + off, m * 8, hipMemcpyHostToDevice, sc.s_copy));
+      HLC_TRY(hipMemcpyAsync(x.dec + off, x.dec_h + off, m * 8, hipMemcpyHostToDevice, sc.s_copy));
+      HLC_TRY(hipEventRecord(sc.ev_copy, sc.s_copy));
+      HLC_TRY(hipStreamWaitEvent(s, sc.ev_copy, 0));
+      launch_dec_hist(x.ra + off, x.dec + off, (uint32_t)m, STREAM_DEC_BINS, x.hist, x.err, dev->cnt, s);
+    }
+  }
+  std::vector<uint32_t> h_hist(2 * STREAM_DEC_BINS);
+  HLC_TRY(hipMemcpyAsync(h_hist.data(), hist, h_hist.size() * 4, hipMemcpyDeviceToHost, s));
+  HLC_TRY(hipMemcpyAsync(dev->cnt_host, dev->cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HLC_TRY(hipStreamSynchronize(s));
+  if (dev->cnt_host->err) return HLC_E_INVAL;
+
+  // 2. Dec chunks: consecutive histogram bins holding <= CHUNK A sources
+  //    (a single dense bin may exceed it)
+  const int64_t CHUNK = int64_t(1) << 23;
+  std::vector<int32_t> chunk_of_bin(STREAM_DEC_BINS);
+  std::vector<double> edges{-90.0};
+  int64_t acc = 0;
+  int32_t nch = 0;
+  for (int32_t b = 0; b < STREAM_DEC_BINS; ++b) {
+    int64_t c = h_hist[b];
+    if (acc > 0 && acc + c > CHUNK) {
+      edges.push_back(-90.0 + 180.0 * b / STREAM_DEC_BINS);
+      ++nch;
+      acc = 0;
+    }
+    acc += c;
+    chunk_of_bin[b] = nch;
+  }
+  ++nch;
+  edges.push_back(90.0);
+  int32_t* d_cob;
+  double* d_edges;
+  unsigned long long *curA, *curB;
+  HLC_CHECK(sc.alloc(&d_cob, STREAM_DEC_BINS));
+  HLC_CHECK(sc.alloc(&d_edges, edges.size()));
+  HLC_CHECK(sc.alloc(&curA, nch));
+  HLC_CHECK(sc.alloc(&curB, nch));
+  HLC_TRY(hipMemcpyAsync(d_cob, chunk_of_bin.data(), STREAM_DEC_BINS * 4, hipMemcpyHostToDevice, s));
+  HLC_TRY(hipMemcpyAsync(d_edges, edges.data(), edges.size() * 8, hipMemcpyHostToDevice, s));
+  // B counts per chunk including the copies for neighbouring chunks
+  Geom gr;
+  set_radius(gr, r_arcsec);
+  HLC_TRY(hipMemsetAsync(curB, 0, nch * 8, s));
+  launch_chunk_scatter(B_ra, B_dec, (uint32_t)nb, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, gr.rpad_deg,
+                       curB, nullptr, nullptr, nullptr, s);
+  std::vector<unsigned long long> cntB(nch), offA(nch + 1, 0), offB(nch + 1, 0);
+  HLC_TRY(hipMemcpyAsync(cntB.data(), curB, nch * 8, hipMemcpyDeviceToHost, s));
+  HLC_TRY(hipStreamSynchronize(s));
+  for (int32_t b = 0; b < STREAM_DEC_BINS; ++b) offA[chunk_of_bin[b] + 1] += h_hist[b];
+  for (int32_t k = 0; k < nch; ++k) {
+    offA[k + 1] += offA[k];
+    offB[k + 1] = offB[k] + cntB[k];
+  }
+  // 3. chunk-ordered copies with original indices
+  double *CA_ra, *CA_dec, *CB_ra, *CB_dec;
+  uint32_t *CA_idx, *CB_idx;
+  HLC_CHECK(sc.alloc(&CA_ra, na));
+  HLC_CHECK(sc.alloc(&CA_dec, na));
+  HLC_CHECK(sc.alloc(&CA_idx, na));
+  HLC_CHECK(sc.alloc(&CB_ra, offB[nch]));
+  HLC_CHECK(sc.alloc(&CB_dec, offB[nch]));
+  HLC_CHECK(sc.alloc(&CB_idx, offB[nch]));
+  HLC_TRY(hipMemcpyAsync(curA, offA.data(), nch * 8, hipMemcpyHostToDevice, s));
+  HLC_TRY(hipMemcpyAsync(curB, offB.data(), nch * 8, hipMemcpyHostToDevice, s));
+  launch_chunk_scatter(A_ra, A_dec, (uint32_t)na, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, 0.0, curA,
+                       CA_ra, CA_dec, CA_idx, s);
+  launch_chunk_scatter(B_ra, B_dec, (uint32_t)nb, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, gr.rpad_deg,
+                       curB, CB_ra, CB_dec, CB_idx, s);
+
+  // 4. chunks through the core cross-match; pairs leave through the ring
+  int64_t total = 0;
+  int64_t pending[2] = {-1, -1};
+  int32_t slot = 0;
+  auto drain = [&](int h) -> int {
+    if (pending[h] < 0) return HLC_OK;
+    HLC_TRY(hipEventSynchronize(sc.ev_d2h[h]));
+    const int64_t n = pending[h];
+    pending[h] = -1;
+    if (n > 0 && sink(h_pairs[h], (o->flags & HLC_NO_SEP) ? nullptr : h_sep[h], n, user) != 0)
+      return HLC_E_INVAL;
+    return HLC_OK;
+  };
+  struct Work {
+    uint64_t a0, na, b0, nb;
+  };
+  std::vector<Work> todo;
+  for (int32_t k = nch - 1; k >= 0; --k)
+    todo.push_back({offA[k], offA[k + 1] - offA[k], offB[k], offB[k + 1] - offB[k]});
+  hlc_opts co = *o;
+  co.capacity = half;
+  co.flags = o->flags & (HLC_NO_SEP | HLC_PROFILE);
+  int64_t nfound = 0;
+  co.n_pairs = &nfound;
+  while (!todo.empty()) {
+    Work w = todo.back();
+    todo.pop_back();
+    if (w.na == 0 || w.nb == 0) continue;
+    HLC_CHECK(drain(slot));  // this half's previous batch has reached the host
+    hlc_pair* rp = d_pairs + slot * half;
+    double* rs = d_sep + slot * half;
+    int st = xmatch_core(CA_ra + w.a0, CA_dec + w.a0, (int64_t)w.na, CB_ra + w.b0, CB_dec + w.b0,
+                         (int64_t)w.nb, r_arcsec, rp, rs, &co);
+    if (st == HLC_E_OVERFLOW) {
+      if (w.na == 1) return HLC_E_OVERFLOW;  // one source has more pairs than half the ring
+      const uint64_t h1 = w.na / 2;
+      todo.push_back({w.a0 + h1, w.na - h1, w.b0, w.nb});
+      todo.push_back({w.a0, h1, w.b0, w.nb});
+      continue;
+    }
+    if (st != HLC_OK) return st;
+    const int64_t n = nfound;
+    launch_remap_pairs(reinterpret_cast<uint2*>(rp), (uint32_t)n, CA_idx + w.a0, CB_idx + w.b0, s);
+    HLC_TRY(hipEventRecord(sc.ev_done, s));
+    HLC_TRY(hipStreamWaitEvent(sc.s_d2h, sc.ev_done, 0));
+    if (n > 0) {
+      HLC_TRY(hipMemcpyAsync(h_pairs[slot], rp, n * sizeof(hlc_pair), hipMemcpyDeviceToHost, sc.s_d2h));
+      if (!(o->flags & HLC_NO_SEP))
+        HLC_TRY(hipMemcpyAsync(h_sep[slot], rs, n * sizeof(double), hipMemcpyDeviceToHost, sc.s_d2h));
+    }
+    HLC_TRY(hipEventRecord(sc.ev_d2h[slot], sc.s_d2h));
+    pending[slot] = n;
+    total += n;
+    slot ^= 1;
+  }
+  HLC_CHECK(drain(slot));
+  HLC_CHECK(drain(slot ^ 1));
+  std::memset(&g_stats, 0, sizeof(g_stats));
+  g_stats.na = na;
+  g_stats.nb = nb;
+  g_stats.nb_halo = (int64_t)offB[nch];
+  g_stats.n_pairs = total;
+  g_stats.n_zones = nch;  // Dec chunks
+  *o->n_pairs = total;
+  return HLC_OK;
+}
+
+}  // namespace
+}  // namespace hlc
+
+extern "C" {
+
+int hlc_xmatch_stream(const double* a_ra_host, const double* a_dec_host, int64_t na,
+                      const double* b_ra_host, const double* b_dec_host, int64_t nb, double r_arcsec,
+                      hlc_sink sink, void* user, const hlc_opts* opts) {
+  int st = check_common(r_arcsec, na, nb, opts);
+  if (st) return st;
+  if (!sink) return HLC_E_INVAL;
+  if ((na > 0 && (!a_ra_host || !a_dec_host)) || (nb > 0 && (!b_ra_host || !b_dec_host)))
+    return HLC_E_INVAL;
+  if (opts->flags & HLC_SELF) return HLC_E_UNSUPPORTED;
+  try {
+    return stream_impl(a_ra_host, a_dec_host, na, b_ra_host, b_dec_host, nb, r_arcsec, sink, user, opts);
+  } catch (const std::bad_alloc&) {
+    return HLC_E_NOMEM;
+  } catch (...) {
+    return HLC_E_DEVICE;
+  }
 }
 
 const char* hlc_strerror(int status) {
@@ -706,6 +1396,14 @@ int hlc_last_stats(hlc_stats* out) {
 }
 
 void hlc_shutdown(void) {
+  for (auto& B : g_bstate) {
+    drop_graph(B);
+    if (B.tables) (void)hipFree(B.tables);
+    if (B.st) (void)hipStreamDestroy(B.st);
+    for (hipEvent_t e : {B.ev_in, B.ev_out, B.ev_t0, B.ev_t1})
+      if (e) (void)hipEventDestroy(e);
+    B = BatchState();
+  }
   for (auto& d : g_dev) {
     if (!d.init) continue;
     if (d.ws) (void)hipFree(d.ws);

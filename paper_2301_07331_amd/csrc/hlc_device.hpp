@@ -38,6 +38,20 @@ struct Geom {
   int32_t pad_;
 };
 
+// An entry count known on the host (base) plus an optional count that only
+// the device knows yet (B halo copies appended by keygen), capped at the
+// buffer capacity. Kernels read it instead of taking the count from the host,
+// so a call needs no host round-trip before its sort and can be captured.
+// Launch grids are sized from `cap`.
+struct DevCount {
+  uint32_t base, cap;
+  const unsigned long long* extra;
+  __device__ uint32_t get() const {
+    unsigned long long v = (unsigned long long)base + (extra ? *extra : 0ull);
+    return v < cap ? (uint32_t)v : cap;
+  }
+};
+
 // Per-group B candidate ranges (positions in the sorted B arrays).
 struct GroupRanges {
   uint32_t start[MAXR];
@@ -55,7 +69,7 @@ struct Counters {
   unsigned long long n_band;      // entries in the band list
   unsigned long long n_ties;      // decided in double-double
   unsigned int err;               // bit 0: bad coordinate in A, bit 1: in B
-  unsigned int pad_;
+  unsigned int queue;             // work-queue head of persistent kernels
   unsigned long long pad2_[2];
 };
 

@@ -26,23 +26,23 @@ size_t sort_counts_len(uint32_t n);
 size_t sort_block_sums_len(uint32_t n);
 // LSD radix sort of (keys, vals), ascending, stable, on key bits [0, key_bits).
 // The result ends in (keys, vals).
-void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t n, int key_bits, const SortScratch& sc,
+void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
                 hipStream_t s);
 
 void launch_zone_tables(const Geom& g, int32_t* zmarg, double2* zone_cs, double2* super_cs,
                         hipStream_t s);
-void launch_zone_starts(const uint32_t* keys, uint32_t n, const Geom& g, uint32_t* zstart,
+void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s);
-void launch_layout64(const uint32_t* vals, uint32_t n, const double* ra, const double* dec,
+void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s);
-void launch_layout32(const uint32_t* keys, const uint32_t* vals, uint32_t n, const double* ra,
+void launch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,
                      const double* dec, const Geom& g, const double2* zone_cs,
                      const double2* super_cs, Rec32* rec, double2* radec, hipStream_t s);
-void launch_merge_lb(const uint32_t* keysA, uint32_t na, const uint32_t* keysB, uint32_t nb,
-                     uint32_t* lb, hipStream_t s);
-void launch_ranges(const uint32_t* keysA, uint32_t na, const uint32_t* lb, const uint32_t* keysB,
-                   uint32_t nb, const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
-                   double c_r, GroupRanges* out, hipStream_t s);
+void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
+                     const DevCount& nb, uint32_t* lb, hipStream_t s);
+void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
+                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g, double c_r,
+                   GroupRanges* out, hipStream_t s);
 
 // ---- match.hip -------------------------------------------------------------
 struct OutArgs {
@@ -50,13 +50,14 @@ struct OutArgs {
   double* sep;                  // caller buffer or nullptr
   unsigned long long cap;       // capacity in pairs
   uint2* band;                  // band list (original indices, B halo bit cleared)
+  uint32_t* band_job;           // batched form: job of each band entry (else nullptr)
   unsigned long long band_cap;
   Counters* cnt;
 };
 
 struct MatchArgs {
   const GroupRanges* ranges;
-  uint32_t na, nb;
+  DevCount na;
   // FP64 form
   const Rec64* recA64;
   const Rec64* recB64;
@@ -85,5 +86,79 @@ void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s);
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,
                     const double* b_dec, double r_arcsec, double H_lo, double H_hi,
                     const OutArgs& o, hipStream_t s);
+
+// ---- stream.hip ------------------------------------------------------------
+void launch_dec_hist(const double* ra, const double* dec, uint32_t n, int32_t nbins, uint32_t* hist,
+                     uint32_t err_bit, Counters* cnt, hipStream_t s);
+// out_ra == nullptr: count only (cursor[k] += entries of chunk k)
+void launch_chunk_scatter(const double* ra, const double* dec, uint32_t n, uint32_t base_index,
+                          int32_t nbins, const int32_t* chunk_of_bin, const double* edges,
+                          int32_t nchunks, double halo_deg, unsigned long long* cursor,
+                          double* out_ra, double* out_dec, uint32_t* out_idx, hipStream_t s);
+void launch_remap_pairs(uint2* pairs, uint32_t n, const uint32_t* a_idx, const uint32_t* b_idx,
+                        hipStream_t s);
+
+// ---- batch.hip -------------------------------------------------------------
+struct BatchJob {          // one job as given by the caller, plus host-derived fields
+  int64_t a_off, na, b_off, nb;
+  double r_arcsec;
+  double H_lo, H_hi;       // FP64 haversine band of the job's radius
+  uint32_t a_entry, b_entry;  // first packed entry of the job in the A / B key arrays
+  uint32_t zoff, zcap;     // the job's slice of the per-(job, zone) tables; zone budget
+};
+struct BatchTile {         // <= 256 consecutive sources of one job and one side
+  uint32_t job, entry, src, count;
+};
+struct JobGeom {           // the job's local frame (computed on the device)
+  double d0, h_deg, inv_h, ra0, ra_span, bin_scale, r_deg, rpad_deg;
+  double c_r, t_lo64, t_hi64, H_lo, H_hi;
+  double cx, cy, cz;       // FP32 frame centre (snapped)
+  float thr32;
+  int32_t nz, rb, full_ra;
+  uint32_t nbins, zoff;
+};
+struct BatchMatchArgs {
+  const GroupRanges* ranges;
+  const uint32_t* order;   // LPT order of the groups
+  unsigned int* queue;     // work-queue head
+  DevCount na;
+  const uint32_t* keysA;
+  const uint32_t* keysB;
+  const Rec64* recA64;
+  const Rec64* recB64;
+  const Rec32* recA32;
+  const Rec32* recB32;
+  const double2* radecA;
+  const double2* radecB;
+  const JobGeom* geo;
+  int32_t lb_bits;
+  unsigned long long* job_count;
+};
+
+void launch_job_bounds_init(unsigned long long* bounds, int32_t njobs, hipStream_t s);
+void launch_job_bounds(const BatchTile* tiles, uint32_t ntiles, const BatchJob* jobs, const double* a_ra,
+                       const double* b_ra, const double* ra, const double* dec, bool side_b,
+                       unsigned long long* bounds, Counters* cnt, hipStream_t s);
+void launch_job_frames(const BatchJob* jobs, int32_t njobs, const double* a_ra, const double* b_ra,
+                       const unsigned long long* bounds, int32_t lb_bits, double h_factor, JobGeom* geo,
+                       hipStream_t s);
+void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, const JobGeom* geo, const double* ra,
+                         const double* dec, int32_t lb_bits, bool halo, uint32_t n_total, uint32_t* keys,
+                         uint32_t* vals, Counters* cnt, hipStream_t s);
+void launch_batch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,
+                           const double* dec, const JobGeom* geo, int32_t lb_bits, Rec32* rec,
+                           double2* radec, hipStream_t s);
+void launch_batch_zone_tables(const JobGeom* geo, int32_t njobs, const BatchJob* jobs, uint32_t ztotal,
+                              int32_t lb_bits, const uint32_t* keysB, const DevCount& nb, int32_t* zmarg,
+                              uint32_t* zstart, hipStream_t s);
+void launch_batch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
+                         const JobGeom* geo, int32_t lb_bits, const int32_t* zmarg, const uint32_t* zstart,
+                         GroupRanges* out, uint32_t* cost_key, uint32_t* cost_val, hipStream_t s);
+void launch_batch_match(const BatchMatchArgs& a, const OutArgs& o, bool fp32, uint32_t nblocks,
+                        hipStream_t s);
+void launch_batch_certify(const double* a_ra, const double* a_dec, const double* b_ra, const double* b_dec,
+                          const BatchJob* jobs, const OutArgs& o, unsigned long long* job_count,
+                          hipStream_t s);
+void launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t s);
 
 }  // namespace hlc

@@ -158,7 +158,7 @@ __device__ inline void cursor_advance(Cursor& c, const GroupRanges* R) {
   cursor_seek(c, R);
 }
 
-__global__ __launch_bounds__(MT) void k_match64(MatchArgs a, OutArgs o, uint32_t ngroups) {
+__global__ __launch_bounds__(MT) void k_match64(MatchArgs a, OutArgs o) {
   __shared__ uint2 s_q[WAVES][QCAP];
   const uint32_t lane = lane_id();
   const uint32_t w = threadIdx.x >> 6;
@@ -168,10 +168,12 @@ __global__ __launch_bounds__(MT) void k_match64(MatchArgs a, OutArgs o, uint32_t
   uint2* q = s_q[w];
   uint32_t qn = 0;
 
+  const uint32_t na = a.na.get();
+  const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   const bool grp_ok = grp < ngroups;
   const GroupRanges* R = grp_ok ? a.ranges + grp : nullptr;
   const uint32_t a_pos = grp * GROUP + l16;
-  bool a_ok = grp_ok && a_pos < a.na;
+  bool a_ok = grp_ok && a_pos < na;
   double ax = 0.0, ay = 0.0, az = 0.0;
   if (a_ok) {
     Rec64 A = a.recA64[a_pos];
@@ -252,7 +254,7 @@ __device__ inline void steps32(float ax, float ay, float az, bool a_ok, const fl
   if constexpr (N + 1 < GROUP) steps32<N + 1>(ax, ay, az, a_ok, b, thr, a_pos, b_pos0, q, qn);
 }
 
-__global__ __launch_bounds__(MT) void k_match32(MatchArgs a, OutArgs o, uint32_t ngroups) {
+__global__ __launch_bounds__(MT) void k_match32(MatchArgs a, OutArgs o) {
   __shared__ uint2 s_q[WAVES][QCAP];
   const uint32_t lane = lane_id();
   const uint32_t w = threadIdx.x >> 6;
@@ -262,10 +264,12 @@ __global__ __launch_bounds__(MT) void k_match32(MatchArgs a, OutArgs o, uint32_t
   uint2* q = s_q[w];
   uint32_t qn = 0;
 
+  const uint32_t na = a.na.get();
+  const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   const bool grp_ok = grp < ngroups;
   const GroupRanges* R = grp_ok ? a.ranges + grp : nullptr;
   const uint32_t a_pos = grp * GROUP + l16;
-  bool a_ok = grp_ok && a_pos < a.na;
+  bool a_ok = grp_ok && a_pos < na;
   // reference cell: the group's first A source
   double c0x = 0.0, c0y = 0.0, c0z = 0.0;
   if (grp_ok) cell_centre(a, a.keysA[grp * GROUP], c0x, c0y, c0z);
@@ -347,17 +351,17 @@ __global__ __launch_bounds__(256) void k_certify(const double* __restrict__ a_ra
 }  // namespace
 
 void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
-  uint32_t ngroups = (a.na + GROUP - 1) / GROUP;
+  uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
   if (ngroups == 0) return;
   uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
-  k_match64<<<blocks, MT, 0, s>>>(a, o, ngroups);
+  k_match64<<<blocks, MT, 0, s>>>(a, o);
 }
 
 void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
-  uint32_t ngroups = (a.na + GROUP - 1) / GROUP;
+  uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
   if (ngroups == 0) return;
   uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
-  k_match32<<<blocks, MT, 0, s>>>(a, o, ngroups);
+  k_match32<<<blocks, MT, 0, s>>>(a, o);
 }
 
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,

@@ -91,10 +91,11 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
 // LSD radix sort (8-bit digits)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                           uint32_t n, int shift,
+                                                           DevCount nc, int shift,
                                                            uint32_t* __restrict__ counts,
                                                            uint32_t ntiles) {
   __shared__ uint32_t h[4][RS_BINS];
+  const uint32_t n = nc.get();
   const uint32_t t = threadIdx.x, w = t >> 6;
   for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&h[0][0])[k] = 0u;
   __syncthreads();
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_scan_down(const uint32_t* in,
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, uint32_t n, int shift,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, DevCount nc, int shift,
     const uint32_t* __restrict__ offsets, uint32_t ntiles) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[RS_TILE];
@@ -192,6 +193,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * RS_TILE;
+  const uint32_t n = nc.get();
+  if (base >= n) return;  // tile beyond the device-side count (block-uniform)
   const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
 
   for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
@@ -304,8 +307,9 @@ __device__ inline uint32_t lower_bound_u32(const uint32_t* keys, uint32_t lo, ui
 }
 
 // zstart[z] = first position of zone z in the sorted keys; zstart[nz] = n
-__global__ void k_zone_starts(const uint32_t* __restrict__ keys, uint32_t n, Geom g,
+__global__ void k_zone_starts(const uint32_t* __restrict__ keys, DevCount nc, Geom g,
                               uint32_t* __restrict__ zstart) {
+  const uint32_t n = nc.get();
   uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z > (uint32_t)g.nz) return;
   if (z == (uint32_t)g.nz) { zstart[z] = n; return; }
@@ -324,12 +328,12 @@ __device__ inline void unit_vector(double ra, double dec, double& x, double& y, 
   z = sd;
 }
 
-__global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ vals, uint32_t n,
+__global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
                                                   Rec64* __restrict__ rec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= nc.get()) return;
   uint32_t v = vals[p];
   uint32_t i = v & IDX_MASK;
   double x, y, z;
@@ -357,7 +361,7 @@ __device__ inline void cell_centre(const Geom& g, const double2* zone_cs, const 
 }
 
 __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ keys,
-                                                  const uint32_t* __restrict__ vals, uint32_t n,
+                                                  const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec, Geom g,
                                                   const double2* __restrict__ zone_cs,
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ k
                                                   Rec32* __restrict__ rec,
                                                   double2* __restrict__ radec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= nc.get()) return;
   uint32_t v = vals[p];
   uint32_t i = v & IDX_MASK;
   double a = ra[i], d = dec[i];
@@ -400,14 +404,16 @@ __device__ inline uint32_t merge_split(const uint32_t* A, uint32_t na, const uin
   return lo;
 }
 
-__global__ __launch_bounds__(MP_THREADS) void k_merge_lb(const uint32_t* __restrict__ A, uint32_t na,
-                                                         const uint32_t* __restrict__ B, uint32_t nb,
+__global__ __launch_bounds__(MP_THREADS) void k_merge_lb(const uint32_t* __restrict__ A, DevCount nac,
+                                                         const uint32_t* __restrict__ B, DevCount nbc,
                                                          uint32_t* __restrict__ lb) {
   __shared__ uint32_t sA[MP_TILE];
   __shared__ uint32_t sB[MP_TILE];
   __shared__ uint32_t s_split[2];
+  const uint32_t na = nac.get(), nb = nbc.get();
   const uint64_t total = (uint64_t)na + nb;
   const uint32_t d0 = blockIdx.x * MP_TILE;
+  if ((uint64_t)d0 >= total) return;  // beyond the device-side counts (block-uniform)
   const uint32_t d1 = (uint32_t)min((uint64_t)d0 + MP_TILE, total);
   if (threadIdx.x < 2) s_split[threadIdx.x] = merge_split(A, na, B, nb, threadIdx.x == 0 ? d0 : d1);
   __syncthreads();
@@ -492,13 +498,14 @@ struct RangeList {
   }
 };
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keysA, uint32_t na,
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keysA, DevCount nac,
                                                 const uint32_t* __restrict__ lb,
-                                                const uint32_t* __restrict__ keysB, uint32_t nb,
+                                                const uint32_t* __restrict__ keysB,
                                                 const uint32_t* __restrict__ zstartB,
                                                 const int32_t* __restrict__ zmarg, Geom g,
-                                                double c_r, GroupRanges* __restrict__ out,
-                                                uint32_t ngroups) {
+                                                double c_r, GroupRanges* __restrict__ out) {
+  const uint32_t na = nac.get();
+  const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
   if (grp >= ngroups) return;
   const uint32_t p0 = grp * GROUP;
@@ -601,8 +608,9 @@ void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& 
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
 size_t sort_block_sums_len(uint32_t n) { return std::max<size_t>(1, cdiv(sort_counts_len(n), SCAN_TILE)); }
 
-void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t n, int key_bits, const SortScratch& sc,
+void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
                 hipStream_t s) {
+  const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
   if (n <= 1) return;
   const uint32_t ntiles = cdiv(n, RS_TILE);
   const uint32_t nc = RS_BINS * ntiles;
@@ -611,11 +619,11 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t n, int key_bits, const 
   int passes = (key_bits + 7) / 8;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, n, shift, sc.counts, ntiles);
+    k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles);
     k_scan_reduce<<<nsb, RS_THREADS, 0, s>>>(sc.counts, nc, sc.block_sums);
     k_scan_top<<<1, RS_THREADS, 0, s>>>(sc.block_sums, nsb);
     k_scan_down<<<nsb, RS_THREADS, 0, s>>>(sc.counts, sc.counts, nc, sc.block_sums);
-    k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, n, shift, sc.counts, ntiles);
+    k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts, ntiles);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
@@ -631,38 +639,37 @@ void launch_zone_tables(const Geom& g, int32_t* zmarg, double2* zone_cs, double2
   k_zone_tables<<<cdiv(n, 256), 256, 0, s>>>(g, zmarg, zone_cs, super_cs);
 }
 
-void launch_zone_starts(const uint32_t* keys, uint32_t n, const Geom& g, uint32_t* zstart,
+void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s) {
   k_zone_starts<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(keys, n, g, zstart);
 }
 
-void launch_layout64(const uint32_t* vals, uint32_t n, const double* ra, const double* dec,
+void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s) {
-  if (n == 0) return;
-  k_layout64<<<cdiv(n, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
+  if (n.cap == 0) return;
+  k_layout64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
 }
 
-void launch_layout32(const uint32_t* keys, const uint32_t* vals, uint32_t n, const double* ra,
+void launch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,
                      const double* dec, const Geom& g, const double2* zone_cs,
                      const double2* super_cs, Rec32* rec, double2* radec, hipStream_t s) {
-  if (n == 0) return;
-  k_layout32<<<cdiv(n, 256), 256, 0, s>>>(keys, vals, n, ra, dec, g, zone_cs, super_cs, rec, radec);
+  if (n.cap == 0) return;
+  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(keys, vals, n, ra, dec, g, zone_cs, super_cs, rec, radec);
 }
 
-void launch_merge_lb(const uint32_t* keysA, uint32_t na, const uint32_t* keysB, uint32_t nb,
-                     uint32_t* lb, hipStream_t s) {
-  if (na == 0) return;
-  uint32_t blocks = cdiv((uint64_t)na + nb, MP_TILE);
+void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
+                     const DevCount& nb, uint32_t* lb, hipStream_t s) {
+  if (na.cap == 0) return;
+  uint32_t blocks = cdiv((uint64_t)na.cap + nb.cap, MP_TILE);
   k_merge_lb<<<blocks, MP_THREADS, 0, s>>>(keysA, na, keysB, nb, lb);
 }
 
-void launch_ranges(const uint32_t* keysA, uint32_t na, const uint32_t* lb, const uint32_t* keysB,
-                   uint32_t nb, const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
-                   double c_r, GroupRanges* out, hipStream_t s) {
-  uint32_t ngroups = cdiv(na, GROUP);
+void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
+                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g, double c_r,
+                   GroupRanges* out, hipStream_t s) {
+  uint32_t ngroups = cdiv(na.cap, GROUP);
   if (ngroups == 0) return;
-  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, nb, zstartB, zmarg, g, c_r, out,
-                                              ngroups);
+  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, zstartB, zmarg, g, c_r, out);
 }
 
 }  // namespace hlc

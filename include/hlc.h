@@ -123,6 +123,17 @@ int hlc_xmatch(const double *a_ra, const double *a_dec, int64_t na, const double
                const double *b_dec, int64_t nb, double r_arcsec, hlc_pair *out_pairs,
                double *out_sep_arcsec, const hlc_opts *opts);
 
+/* Eq. (4) with per-source error radii: report (i, j) iff the separation is
+ * at most k_sigma * sqrt(a_err[i]^2 + b_err[j]^2) arcsec (the paper uses
+ * k_sigma = 3). a_err [na], b_err [nb]: device FP64 arcsec, finite, >= 0.
+ * The largest such radius must not exceed 3600 arcsec. Pairs are certified
+ * at their own radius exactly as hlc_xmatch certifies at r. Other arguments,
+ * outputs and errors as hlc_xmatch (HLC_SELF is not supported).           */
+int hlc_xmatch_radii(const double *a_ra, const double *a_dec, const double *a_err, int64_t na,
+                     const double *b_ra, const double *b_dec, const double *b_err, int64_t nb,
+                     double k_sigma, hlc_pair *out_pairs, double *out_sep_arcsec,
+                     const hlc_opts *opts);
+
 /* Reusable device index of one catalogue (section 4.2's first-level
  * partition: positions grouped by Dec zone, then RA). An index built for
  * radius r can serve as either side of hlc_xmatch_part at any radius <= r

@@ -54,6 +54,10 @@ def _load():
             f.restype = C.c_void_p
             f.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                           C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        lib.oracle_xmatch_radii.restype = C.c_void_p
+        lib.oracle_xmatch_radii.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int, C.c_int,
+                                            C.POINTER(C.c_int)]
         lib.oracle_brute.restype = C.c_void_p
         lib.oracle_brute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_int64, C.c_double, C.c_int, C.POINTER(C.c_int)]
@@ -127,6 +131,21 @@ def brute(a_ra, a_dec, b_ra, b_dec, r_arcsec: float, nthreads: int = 0) -> Resul
     t0 = time.perf_counter()
     h = lib.oracle_brute(a_ra.ctypes.data, a_dec.ctypes.data, len(a_ra), b_ra.ctypes.data,
                          b_dec.ctypes.data, len(b_ra), float(r_arcsec), int(nthreads), C.byref(st))
+    if st.value != 0 or not h:
+        raise OracleError("invalid input")
+    return _collect(lib, h, t0)
+
+
+def xmatch_radii(a_ra, a_dec, a_err, b_ra, b_dec, b_err, k: float = 3.0, nthreads: int = 0,
+                 brute: bool = False) -> Result:
+    """Eq. (4) with per-source error radii: theta <= k sqrt(ea^2 + eb^2) arcsec."""
+    lib = _load()
+    a_ra, a_dec, a_err, b_ra, b_dec, b_err = map(_f64, (a_ra, a_dec, a_err, b_ra, b_dec, b_err))
+    st = C.c_int(0)
+    t0 = time.perf_counter()
+    h = lib.oracle_xmatch_radii(a_ra.ctypes.data, a_dec.ctypes.data, a_err.ctypes.data, len(a_ra),
+                                b_ra.ctypes.data, b_dec.ctypes.data, b_err.ctypes.data, len(b_ra), float(k),
+                                int(nthreads), 1 if brute else 0, C.byref(st))
     if st.value != 0 or not h:
         raise OracleError("invalid input")
     return _collect(lib, h, t0)

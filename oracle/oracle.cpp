@@ -155,6 +155,21 @@ int decide(double ra1, double dec1, double cd1, double ra2, double dec2, double 
   return fabsq(diff) <= TIE_REL * t.Hq ? IN_TIE : IN_QUAD;
 }
 
+// Per-pair threshold of eq. (4): r_ij = k * sqrt(ea_i^2 + eb_j^2) arcsec.
+// H = sin^2(r_ij / 2) in FP64 has a relative error of a few u (sqrt and the
+// products add < 4u to the 11u of make_thresh), inside the same EPS_BAND.
+Thresh thresh_pair(double k, double ea, double eb) {
+  Thresh t;
+  double r_as = k * std::sqrt(ea * ea + eb * eb);
+  t.r_deg = r_as / 3600.0;
+  double s = std::sin(t.r_deg * K64 * 0.5);
+  t.H = s * s;
+  quad rq = (quad)k * sqrtq((quad)ea * (quad)ea + (quad)eb * (quad)eb) / 3600;
+  quad sq = sinq(rq * (M_PIq / 180) / 2);
+  t.Hq = sq * sq;
+  return t;
+}
+
 struct Hit {
   uint32_t a, b;
   double sep;
@@ -330,6 +345,81 @@ oracle_result* oracle_xmatch(const double* a_ra, const double* a_dec, int64_t na
     res->st.ties += s.ties;
   }
   finish(res, parts, sort_pairs != 0);
+  return res;
+}
+
+// Per-source error radii (eq. (4)): pairs with theta <= k sqrt(ea_i^2 + eb_j^2)
+// arcsec. Candidates come from the zone join at the largest such radius;
+// `brute` != 0 runs all m*n pairs instead.
+oracle_result* oracle_xmatch_radii(const double* a_ra, const double* a_dec, const double* a_err,
+                                   int64_t na, const double* b_ra, const double* b_dec,
+                                   const double* b_err, int64_t nb, double k, int nthreads, int brute,
+                                   int* status) {
+  *status = -1;
+  if (na < 0 || nb < 0 || na >= (int64_t(1) << 31) || nb >= (int64_t(1) << 31)) return nullptr;
+  if (!(k > 0.0) || !std::isfinite(k)) return nullptr;
+  int nt = resolve_threads(nthreads);
+  omp_set_num_threads(nt);
+  if (!check_inputs(a_ra, a_dec, na) || !check_inputs(b_ra, b_dec, nb)) return nullptr;
+  double ea_max = 0.0, eb_max = 0.0;
+  for (int64_t i = 0; i < na; ++i) {
+    if (!(a_err[i] >= 0.0) || !std::isfinite(a_err[i])) return nullptr;
+    ea_max = std::max(ea_max, a_err[i]);
+  }
+  for (int64_t j = 0; j < nb; ++j) {
+    if (!(b_err[j] >= 0.0) || !std::isfinite(b_err[j])) return nullptr;
+    eb_max = std::max(eb_max, b_err[j]);
+  }
+  const double rmax = k * std::sqrt(ea_max * ea_max + eb_max * eb_max) * (1.0 + 1e-12);
+  if (!(rmax <= 3600.0)) return nullptr;
+  auto* res = new oracle_result();
+  *status = 0;
+  if (na == 0 || nb == 0) return res;
+  std::vector<std::vector<Hit>> parts(nt);
+  std::vector<Stats> tst(nt);
+  auto one = [&](int tid, int64_t i, int64_t j) {
+    const Thresh t = thresh_pair(k, a_err[i], b_err[j]);  // H = 0 keeps identical points
+    double sep;
+    int o = decide(a_ra[i], a_dec[i], cos_dec64(a_dec[i]), b_ra[j], b_dec[j], cos_dec64(b_dec[j]), t, &sep);
+    ++tst[tid].candidates;
+    if (o == IN_QUAD || o == IN_TIE || o == OUT_QUAD) ++tst[tid].band;
+    if (o == IN_TIE) ++tst[tid].ties;
+    if (o == IN_FP64 || o == IN_QUAD || o == IN_TIE) parts[tid].push_back(Hit{(uint32_t)i, (uint32_t)j, sep});
+  };
+  if (brute) {
+#pragma omp parallel num_threads(nt)
+    {
+      int tid = omp_get_thread_num();
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t i = 0; i < na; ++i)
+        for (int64_t j = 0; j < nb; ++j) one(tid, i, j);
+    }
+  } else {
+    // candidates from the zone join at rmax (its pairs are a superset)
+    int st2 = 0;
+    // (with all errors zero only identical points match; any positive join
+    // radius finds them)
+    oracle_result* cand = oracle_xmatch(a_ra, a_dec, na, b_ra, b_dec, nb, std::max(rmax, 1e-6), nt, 0, &st2);
+    if (!cand) {
+      delete res;
+      *status = -1;
+      return nullptr;
+    }
+    const int64_t nc = (int64_t)cand->hits.size();
+#pragma omp parallel num_threads(nt)
+    {
+      int tid = omp_get_thread_num();
+#pragma omp for schedule(static)
+      for (int64_t c = 0; c < nc; ++c) one(tid, cand->hits[c].a, cand->hits[c].b);
+    }
+    delete cand;
+  }
+  for (auto& st : tst) {
+    res->st.candidates += st.candidates;
+    res->st.band += st.band;
+    res->st.ties += st.ties;
+  }
+  finish(res, parts, true);
   return res;
 }
 

@@ -272,8 +272,8 @@ struct MatchWs {
 
 // Everything after the partition: ranges, match, certification.
 void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_arcsec, bool fp32,
-           bool skip_halo_a, bool self_only, const Tables& tb, const MatchWs& w, hlc_pair* out_pairs,
-           double* out_sep, uint64_t cap, bool prof, hipStream_t s) {
+           bool skip_halo_a, bool self_only, const Radii& rad, const Tables& tb, const MatchWs& w,
+           hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, hipStream_t s) {
   Thresholds th = thresholds(r_arcsec);
   launch_zone_tables(g, w.zmarg, tb.zone_cs, nullptr, s);
   const uint32_t* zstart = w.zstartB;
@@ -304,6 +304,9 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.H_hi = th.H_hi;
   ma.skip_halo_a = skip_halo_a ? 1 : 0;
   ma.self_only = self_only ? 1 : 0;
+  ma.a_err = rad.a_err;
+  ma.b_err = rad.b_err;
+  ma.k_sigma = rad.k;
   OutArgs oa{};
   oa.pairs = reinterpret_cast<uint2*>(out_pairs);
   oa.sep = out_sep;
@@ -314,7 +317,7 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   if (fp32) launch_match32(ma, oa, s);
   else launch_match64(ma, oa, s);
   if (prof) (void)hipEventRecord(dev.ev[9], s);
-  launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, oa, s);
+  launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, s);
   if (prof) (void)hipEventRecord(dev.ev[10], s);
 }
 
@@ -400,7 +403,8 @@ int read_counters(Device& dev, hipStream_t s, bool prof) {
 
 int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
                 const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
-                double* out_sep, const hlc_opts* o, uint64_t band_cap, uint64_t* band_needed) {
+                double* out_sep, const hlc_opts* o, uint64_t band_cap, uint64_t* band_needed,
+                const Radii& rad) {
   *band_needed = 0;
   Device* dev = nullptr;
   HLC_CHECK(get_device(&dev));
@@ -445,7 +449,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   } else {
     HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, tb, sc, 1u, A, slA, s));
   }
-  match(*dev, A, B, g, r_arcsec, fp32, self, self, tb, w, out_pairs,
+  match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, tb, w, out_pairs,
         (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, s);
   HLC_CHECK(read_counters(*dev, s, prof));
 
@@ -467,12 +471,12 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
 // xmatch_impl with the band-list retry.
 int xmatch_core(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
                 const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
-                double* out_sep, const hlc_opts* o) {
+                double* out_sep, const hlc_opts* o, const Radii& rad = Radii{nullptr, nullptr, 0.0}) {
   uint64_t band_cap = (1u << 20) + (uint64_t)(na + nb) / 64;
   for (int attempt = 0; attempt < 3; ++attempt) {
     uint64_t need = 0;
     int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, band_cap,
-                         &need);
+                         &need, rad);
     if (need == 0) return st;
     band_cap = need + need / 4 + 1024;
   }
@@ -533,6 +537,49 @@ int hlc_xmatch(const double* a_ra, const double* a_dec, int64_t na, const double
   try {
     if (na == 0 || nb == 0) return validate_only(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, opts);
     return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep_arcsec, opts);
+  } catch (const std::bad_alloc&) {
+    return HLC_E_NOMEM;
+  } catch (...) {
+    return HLC_E_DEVICE;
+  }
+}
+
+int hlc_xmatch_radii(const double* a_ra, const double* a_dec, const double* a_err, int64_t na,
+                     const double* b_ra, const double* b_dec, const double* b_err, int64_t nb,
+                     double k_sigma, hlc_pair* out_pairs, double* out_sep_arcsec, const hlc_opts* opts) {
+  int st = check_common(1.0, na, nb, opts);
+  if (st) return st;
+  if (!(k_sigma > 0.0) || !(k_sigma < 1e300)) return HLC_E_INVAL;
+  if ((na > 0 && (!a_ra || !a_dec || !a_err)) || (nb > 0 && (!b_ra || !b_dec || !b_err))) return HLC_E_INVAL;
+  if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
+    return HLC_E_INVAL;
+  if (opts->flags & HLC_SELF) return HLC_E_UNSUPPORTED;
+  try {
+    if (na == 0 || nb == 0) return validate_only(a_ra, a_dec, na, b_ra, b_dec, nb, 1.0, opts);
+    // largest radius: filter radius of the whole call (one read-back)
+    Device* dev = nullptr;
+    HLC_CHECK(get_device(&dev));
+    hipStream_t s = (hipStream_t)opts->stream;
+    HLC_CHECK(ensure_ws(*dev, 1024));
+    unsigned long long* codes = (unsigned long long*)dev->ws;
+    launch_zero_counters(dev->cnt, s);
+    launch_zero_u64(codes, 2, s);
+    launch_err_max(a_err, (uint32_t)na, codes, dev->cnt, s);
+    launch_err_max(b_err, (uint32_t)nb, codes + 1, dev->cnt, s);
+    unsigned long long h_codes[2];
+    HLC_TRY(hipMemcpyAsync(h_codes, codes, sizeof h_codes, hipMemcpyDeviceToHost, s));
+    HLC_CHECK(read_counters(*dev, s, false));
+    if (dev->cnt_host->err) return HLC_E_INVAL;
+    double ea, eb;
+    std::memcpy(&ea, &h_codes[0], 8);
+    std::memcpy(&eb, &h_codes[1], 8);
+    double rmax = k_sigma * std::sqrt(ea * ea + eb * eb) * (1.0 + 1e-12);
+    if (!(rmax <= 3600.0)) return HLC_E_INVAL;
+    // all errors zero: only identical positions match; any positive filter
+    // radius finds them
+    rmax = std::max(rmax, 1e-6);
+    return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, rmax, out_pairs, out_sep_arcsec, opts,
+                       Radii{a_err, b_err, k_sigma});
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {
@@ -664,7 +711,8 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       w.zstartB = B->zstart;
       if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
       launch_zero_counters(dev->cnt, s);
-      match(*dev, A->side, B->side, g, r_arcsec, fp32, true, false, A->tb, w, out_pairs,
+      match(*dev, A->side, B->side, g, r_arcsec, fp32, true, false, Radii{nullptr, nullptr, 0.0}, A->tb, w,
+            out_pairs,
             (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec, (uint64_t)opts->capacity, prof, s);
       HLC_CHECK(read_counters(*dev, s, prof));
       const Counters& h = *dev->cnt_host;

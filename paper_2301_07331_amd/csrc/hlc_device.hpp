@@ -252,6 +252,26 @@ __device__ inline dd haversine_dd(double ra1, double dec1, double ra2, double de
   return dd_add(dd_mul(s1, s1), dd_mul(cc, dd_mul(s2, s2)));
 }
 
+__device__ inline dd dd_sqrt(dd x) {
+  if (!(x.hi > 0.0)) return {0.0, 0.0};
+  const double r = sqrt(x.hi);
+  const double p = r * r;
+  const double pe = fma(r, r, -p);
+  const dd d = dd_add(x, dd{-p, -pe});
+  return quick_two_sum(r, d.hi / (2.0 * r));
+}
+
+// sin^2(r/2) for the eq. (4) radius r = k sqrt(ea^2 + eb^2) arcsec, in
+// double-double.
+__device__ inline dd threshold_pair_dd(double k, double ea, double eb) {
+  const dd ea2 = dd_mul(dd{ea, 0.0}, dd{ea, 0.0});
+  const dd eb2 = dd_mul(dd{eb, 0.0}, dd{eb, 0.0});
+  const dd r_as = dd_mul_d(dd_sqrt(dd_add(ea2, eb2)), k);
+  const dd r = dd_div_d(r_as, 3600.0);
+  const dd s = dd_sin(dd_mul_d(dd_deg2rad(r), 0.5));
+  return dd_mul(s, s);
+}
+
 // sin^2(r/2) with r = r_arcsec / 3600 degrees, in double-double.
 __device__ inline dd threshold_dd(double r_arcsec) {
   dd r = dd_div_d(dd{r_arcsec, 0.0}, 3600.0);

@@ -77,6 +77,18 @@ struct MatchArgs {
   int skip_halo_a;
   // self-match: A and B are one catalogue; keep pairs with a < b only
   int self_only;
+  // eq. (4) per-source error radii (else nullptr): the filter ran at the
+  // largest radius; each candidate is decided at k sqrt(ea^2 + eb^2)
+  const double* a_err;
+  const double* b_err;
+  double k_sigma;
+};
+
+// Error radii of one call (nullptr a_err: a single radius).
+struct Radii {
+  const double* a_err;
+  const double* b_err;
+  double k;
 };
 
 void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s);
@@ -85,7 +97,11 @@ void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s);
 // then double-double inside the FP64 band.
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,
                     const double* b_dec, double r_arcsec, double H_lo, double H_hi,
-                    const OutArgs& o, hipStream_t s);
+                    const Radii& rad, const OutArgs& o, hipStream_t s);
+// codes (order-preserving) of the largest error of each side; err bit 8 on a
+// negative or non-finite error
+void launch_err_max(const double* err, uint32_t n, unsigned long long* out_code, Counters* cnt,
+                    hipStream_t s);
 
 // ---- stream.hip ------------------------------------------------------------
 void launch_dec_hist(const double* ra, const double* dec, uint32_t n, int32_t nbins, uint32_t* hist,

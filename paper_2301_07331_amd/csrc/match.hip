@@ -49,6 +49,31 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
   return x * q + min(x, r) + k;
 }
 
+// Thresholds of the eq. (4) radius of one pair (arcsec): chord^2 bounds of
+// the FP64 filter and the haversine band. r carries <= 3u from the sqrt and
+// products and the degree sine <= 3u, so 32u margins hold.
+__device__ inline double pair_radius(const MatchArgs& a, uint32_t ia, uint32_t ib) {
+  const double ea = a.a_err[ia], eb = a.b_err[ib];
+  return a.k_sigma * sqrt(ea * ea + eb * eb);
+}
+__device__ inline void pair_chord_thr(double r_as, double& tlo, double& thi) {
+  double s, c;
+  sincos_deg(0.5 * r_as * (1.0 / 3600.0), &s, &c);
+  const double U = 1.1102230246251565e-16, ETA = 4e-15;
+  const double cr = 2.0 * s;
+  const double hi = cr * (1.0 + 32.0 * U) + ETA;
+  thi = hi * hi * (1.0 + 32.0 * U);
+  const double lo = cr * (1.0 - 32.0 * U) - ETA;
+  tlo = lo > 0 ? lo * lo * (1.0 - 32.0 * U) : -1.0;
+}
+__device__ inline void pair_hav_thr(double r_as, double& Hlo, double& Hhi) {
+  double s, c;
+  sincos_deg(0.5 * r_as * (1.0 / 3600.0), &s, &c);
+  const double H = s * s;
+  Hlo = H * (1.0 - EPS_BAND);
+  Hhi = H * (1.0 + EPS_BAND);
+}
+
 __device__ inline void emit_pairs(bool in, uint32_t ia, uint32_t ib, double sep, const OutArgs& o) {
   uint64_t m = __ballot(in);
   if (m == 0) return;
@@ -102,8 +127,10 @@ __device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2
       // zone: only entries of the A source's own zone count
       const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
       const bool keep = same_zone && (!a.self_only || ia < ib);
-      in = keep && d2 <= a.t_lo64;
-      band = keep && !in && d2 <= a.t_hi64;
+      double tlo = a.t_lo64, thi = a.t_hi64;
+      if (a.a_err) pair_chord_thr(pair_radius(a, ia, ib), tlo, thi);
+      in = keep && d2 <= tlo;
+      band = keep && !in && d2 <= thi;
       if (in) sep = 2.0 * asin(0.5 * sqrt(d2)) * RAD2ARCSEC;
     }
     emit_pairs(in, ia, ib, sep, o);
@@ -230,8 +257,10 @@ __device__ inline void flush32(const MatchArgs& a, const OutArgs& o, const uint2
       double h = haversine64(pa.x, pa.y, pb.x, pb.y);
       const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
       const bool keep = same_zone && (!a.self_only || ia < ib);
-      in = keep && h < a.H_lo;
-      band = keep && !in && h <= a.H_hi;
+      double Hlo = a.H_lo, Hhi = a.H_hi;
+      if (a.a_err) pair_hav_thr(pair_radius(a, ia, ib), Hlo, Hhi);
+      in = keep && h < Hlo;
+      band = keep && !in && h <= Hhi;
       if (in) sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
     }
     emit_pairs(in, ia, ib, sep, o);
@@ -315,7 +344,7 @@ __global__ __launch_bounds__(256) void k_certify(const double* __restrict__ a_ra
                                                  const double* __restrict__ a_dec,
                                                  const double* __restrict__ b_ra,
                                                  const double* __restrict__ b_dec, double r_arcsec,
-                                                 double H_lo, double H_hi, OutArgs o) {
+                                                 double H_lo, double H_hi, Radii rad, OutArgs o) {
   unsigned long long n = o.cnt->n_band;
   if (n > o.band_cap) n = o.band_cap;
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -323,14 +352,19 @@ __global__ __launch_bounds__(256) void k_certify(const double* __restrict__ a_ra
     uint2 e = o.band[i];
     double ra1 = a_ra[e.x], de1 = a_dec[e.x], ra2 = b_ra[e.y], de2 = b_dec[e.y];
     double h = haversine64(ra1, de1, ra2, de2);
+    double Hlo = H_lo, Hhi = H_hi;
+    if (rad.a_err) {
+      const double ea = rad.a_err[e.x], eb = rad.b_err[e.y];
+      pair_hav_thr(rad.k * sqrt(ea * ea + eb * eb), Hlo, Hhi);
+    }
     bool in = false;
     double sep = 0.0;
-    if (h < H_lo) {
+    if (h < Hlo) {
       in = true;
       sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
-    } else if (h <= H_hi) {
+    } else if (h <= Hhi) {
       dd hd = haversine_dd(ra1, de1, ra2, de2);
-      dd Hd = threshold_dd(r_arcsec);
+      dd Hd = rad.a_err ? threshold_pair_dd(rad.k, rad.a_err[e.x], rad.b_err[e.y]) : threshold_dd(r_arcsec);
       dd diff = dd_add(hd, dd_neg(Hd));
       atomicAdd(&o.cnt->n_ties, 1ull);
       if (diff.hi <= TIE_REL * Hd.hi) {
@@ -366,8 +400,8 @@ void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
 
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,
                     const double* b_dec, double r_arcsec, double H_lo, double H_hi,
-                    const OutArgs& o, hipStream_t s) {
-  k_certify<<<256, 256, 0, s>>>(a_ra, a_dec, b_ra, b_dec, r_arcsec, H_lo, H_hi, o);
+                    const Radii& rad, const OutArgs& o, hipStream_t s) {
+  k_certify<<<256, 256, 0, s>>>(a_ra, a_dec, b_ra, b_dec, r_arcsec, H_lo, H_hi, rad, o);
 }
 
 }  // namespace hlc

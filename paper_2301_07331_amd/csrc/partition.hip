@@ -586,11 +586,35 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
   out[grp] = R;
 }
 
+// largest error radius (order-preserving code of a non-negative double is its
+// bit pattern); bit 8 of err flags a negative or non-finite value
+__global__ __launch_bounds__(256) void k_err_max(const double* __restrict__ err, uint32_t n,
+                                                 unsigned long long* __restrict__ out, Counters* cnt) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long c = 0ull;
+  if (i < n) {
+    const double e = err[i];
+    if (e >= 0.0 && e <= 1.0e300) c = (unsigned long long)__double_as_longlong(e);
+    else atomicOr(&cnt->err, 8u);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(c, off);
+    c = o > c ? o : c;
+  }
+  if ((threadIdx.x & 63) == 0 && c) atomicMax(out, c);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void launch_err_max(const double* err, uint32_t n, unsigned long long* out_code, Counters* cnt,
+                    hipStream_t s) {
+  if (n == 0) return;
+  k_err_max<<<cdiv(n, 256), 256, 0, s>>>(err, n, out_code, cnt);
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
   if (n == 0) return;
   uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);

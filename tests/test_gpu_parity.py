@@ -289,3 +289,44 @@ def test_self_match(hlc, prec):
     s = torch.empty(4, dtype=torch.float64, device="cuda")
     st, _ = hlc.hlc_xmatch(t_ra, t_dec, t_ra.clone(), t_dec, 1.0, out, s, flags=hlc.HLC_SELF)
     assert st == hlc.HLC_E_INVAL
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_error_radii(hlc, prec):
+    """Eq. (4): theta <= 3 sqrt(ea^2 + eb^2), per pair, against the oracle."""
+    import torch
+    g = synth.rng(920, 0)
+    for kind in ("dense", "pole", "seam", "dup"):
+        a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 2500, 6, 2.0)
+        ea, eb = g.uniform(0.05, 1.2, len(a_ra)), g.uniform(0.05, 1.2, len(b_ra))
+        ref = oracle.xmatch_radii(a_ra, a_dec, ea, b_ra, b_dec, eb, 3.0)
+        cap = len(ref) + 100
+        out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+        sep = torch.empty(cap, dtype=torch.float64, device="cuda")
+        st, n = hlc.hlc_xmatch_radii(to_dev(a_ra), to_dev(a_dec), to_dev(ea), to_dev(b_ra), to_dev(b_dec),
+                                     to_dev(eb), 3.0, out, sep, precision=prec)
+        assert st == hlc.HLC_OK, hlc.strerror(st)
+        p = out[:n].cpu().numpy().view(np.uint32).reshape(-1, 2)
+        keys = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+        o = np.argsort(keys)
+        assert_same(keys[o], sep[:n].cpu().numpy()[o], ref, label=f"radii {kind}")
+    # Pythagorean radii give exact ties on the meridian; they are matches
+    gg = np.random.default_rng(22)
+    A_ra, A_dec, B_dec = [], [], []
+    for _ in range(200):
+        ra, dec = float(gg.uniform(0, 360)), float(gg.uniform(-80, 80))
+        A_ra.append(ra); A_dec.append(dec); B_dec.append(dec + 3.515625 / 3600.0)
+    A_ra, A_dec, B_dec = map(np.array, (A_ra, A_dec, B_dec))
+    ea, eb = np.full(len(A_ra), 0.703125), np.full(len(A_ra), 0.9375)
+    ref = oracle.xmatch_radii(A_ra, A_dec, ea, A_ra, B_dec, eb, 3.0)
+    out = torch.empty((1000, 2), dtype=torch.int32, device="cuda")
+    sep = torch.empty(1000, dtype=torch.float64, device="cuda")
+    st, n = hlc.hlc_xmatch_radii(to_dev(A_ra), to_dev(A_dec), to_dev(ea), to_dev(A_ra), to_dev(B_dec),
+                                 to_dev(eb), 3.0, out, sep, precision=prec)
+    assert st == hlc.HLC_OK and n == len(ref)
+    assert hlc.last_stats()["n_ties"] > 0
+    bad = eb.copy()
+    bad[3] = -1.0
+    st, _ = hlc.hlc_xmatch_radii(to_dev(A_ra), to_dev(A_dec), to_dev(ea), to_dev(A_ra), to_dev(B_dec),
+                                 to_dev(bad), 3.0, out, sep, precision=prec)
+    assert st == hlc.HLC_E_INVAL

@@ -260,3 +260,83 @@ def test_bad_radius_and_empty():
 def test_ra_360_is_ra_0():
     res = oracle.xmatch(np.array([360.0]), np.array([5.0]), np.array([0.0]), np.array([5.0]), 0.1)
     assert len(res) == 1 and res.sep[0] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# per-source error radii (eq. 4): theta <= k sqrt(ea^2 + eb^2)
+# ---------------------------------------------------------------------------
+def _errs(g, n, lo=0.05, hi=1.2):
+    return g.uniform(lo, hi, n)
+
+
+@pytest.mark.parametrize("kind", ["random", "pole", "seam", "dense", "dup", "same"])
+def test_radii_zone_join_matches_brute_force(kind):
+    g = synth.rng(910, 0)
+    a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 700, 4, 2.0)
+    ea, eb = _errs(g, len(a_ra)), _errs(g, len(b_ra))
+    z = oracle.xmatch_radii(a_ra, a_dec, ea, b_ra, b_dec, eb, 3.0)
+    bf = oracle.xmatch_radii(a_ra, a_dec, ea, b_ra, b_dec, eb, 3.0, brute=True)
+    assert np.array_equal(z.keys(), bf.keys()) and np.array_equal(z.sep, bf.sep)
+    assert len(z) > 0 or kind == "random"
+
+
+def test_radii_exact_pythagorean_ties():
+    """ea = 45/64, eb = 60/64: k sqrt(ea^2 + eb^2) = 3 * 75/64 = 2^-10 deg exactly."""
+    g = np.random.default_rng(21)
+    ea_v, eb_v, r = 0.703125, 0.9375, 3.515625
+    A_ra, A_dec, B_ra, B_dec, truth = [], [], [], [], []
+    for _ in range(60):
+        ra, dec = float(g.uniform(0, 360)), float(g.uniform(-80, 80))
+        for k in range(-2, 3):
+            dd = dec + r / 3600.0
+            for _ in range(abs(k)):
+                dd = float(np.nextafter(dd, math.inf if k > 0 else -math.inf))
+            A_ra.append(ra); A_dec.append(dec); B_ra.append(ra); B_dec.append(dd)
+            truth.append(abs(Fraction(dd) - Fraction(dec)) <= Fraction(r) / 3600)
+    n = len(A_ra)
+    res = oracle.xmatch_radii(A_ra, A_dec, np.full(n, ea_v), B_ra, B_dec, np.full(n, eb_v), 3.0)
+    got = set(int(k) for k in res.keys())
+    for i, t in enumerate(truth):
+        assert ((i << 32) | i in got) == t, i
+    assert res.ties > 0
+    # constant errors reduce to the fixed-radius join
+    fixed = oracle.xmatch(A_ra, A_dec, B_ra, B_dec, r)
+    assert np.array_equal(fixed.keys(), res.keys())
+
+
+def test_radii_per_pair_threshold_against_decimal():
+    g = synth.rng(911, 0)
+    n = 80
+    ra, dec = synth.uniform_sphere(g, n)
+    ea, eb = _errs(g, n), _errs(g, n)
+    rr = 3.0 * np.sqrt(ea * ea + eb * eb)
+    for f in (1 - 1e-9, 1 - 1e-13, 1 + 1e-13, 1 + 1e-9):
+        b_ra, b_dec = synth.direct(ra, dec, rr * f / 3600.0, g.uniform(0, 2 * math.pi, n))
+        res = oracle.xmatch_radii(ra, dec, ea, b_ra, b_dec, eb, 3.0, brute=True)
+        got = set(int(k) for k in res.keys())
+        for i in range(n):
+            from decimal import Decimal, localcontext
+            with localcontext() as c:
+                c.prec = 70
+                r_exact = 3 * (Decimal(ea[i]) ** 2 + Decimal(eb[i]) ** 2).sqrt()
+                h = hp.haversine(ra[i], dec[i], b_ra[i], b_dec[i])
+                s = hp.sin(r_exact / 3600 * hp.pi() / 360)
+                truth = h <= s * s
+            assert ((i << 32) | i in got) == truth, (i, f)
+
+
+def test_radii_invalid_and_zero_errors():
+    one = np.array([1.0])
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch_radii(one, one, np.array([-0.1]), one, one, one, 3.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch_radii(one, one, np.array([float("nan")]), one, one, one, 3.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch_radii(one, one, one, one, one, one, 0.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.xmatch_radii(one, one, np.array([2000.0]), one, one, one, 3.0)  # radius beyond 3600"
+    # zero errors: only identical positions match (theta = 0 <= 0)
+    ra = np.array([10.0, 10.0, 10.0 + 1e-9])
+    dec = np.array([5.0, 5.0, 5.0])
+    res = oracle.xmatch_radii(ra, dec, np.zeros(3), ra[:1], dec[:1], np.zeros(1), 3.0)
+    assert sorted(res.a.tolist()) == [0, 1]

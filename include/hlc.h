@@ -177,9 +177,24 @@ int hlc_xmatch_batch(const hlc_job *jobs, int32_t njobs, const double *a_ra, con
  * abort (the call then returns HLC_E_INVAL). opts->capacity is the ring size
  * in pairs (0 = default); opts->n_pairs receives the total.                 */
 typedef int (*hlc_sink)(const hlc_pair *pairs, const double *sep_arcsec, int64_t n, void *user);
+/* The Dec-chunk size is chosen from the eq. (5) transfer model (measured
+ * once per device): with per-chunk fixed cost s = alpha_h2d + alpha_d2h +
+ * launch overhead and whole-job time W, about sqrt(W / s) chunks balance the
+ * fixed costs against the pipeline's fill and drain.                      */
 int hlc_xmatch_stream(const double *a_ra_host, const double *a_dec_host, int64_t na,
                       const double *b_ra_host, const double *b_dec_host, int64_t nb,
                       double r_arcsec, hlc_sink sink, void *user, const hlc_opts *opts);
+
+/* Host<->device transfer model of eq. (5): T(d) = alpha + beta * d seconds
+ * for d bytes, fitted by least squares to timed pinned-memory copies of 1 B
+ * to 64 MiB on the current device (the alpha/beta measurement procedure of
+ * section 4.1). The streaming form uses it to size its Dec chunks.        */
+typedef struct hlc_transfer {
+  double alpha_h2d, beta_h2d;  /* s, s/byte */
+  double alpha_d2h, beta_d2h;
+  double r2_h2d, r2_d2h;       /* coefficient of determination of each fit */
+} hlc_transfer;
+int hlc_transfer_model(hlc_transfer *out);
 
 const char *hlc_strerror(int status);
 int hlc_last_stats(hlc_stats *out);

@@ -18,7 +18,7 @@ HLC_FP32_RECHECK, HLC_FP64 = 0, 1
 HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF = 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
-           "hlc_xmatch_stream", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
+           "hlc_xmatch_stream", "hlc_transfer_model", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
 
 
 class hlc_tuning(C.Structure):
@@ -45,6 +45,11 @@ class hlc_stats(C.Structure):
 class hlc_job(C.Structure):
     _fields_ = [("a_off", C.c_int64), ("na", C.c_int64), ("b_off", C.c_int64), ("nb", C.c_int64),
                 ("r_arcsec", C.c_double)]
+
+
+class hlc_transfer(C.Structure):
+    _fields_ = [("alpha_h2d", C.c_double), ("beta_h2d", C.c_double), ("alpha_d2h", C.c_double),
+                ("beta_d2h", C.c_double), ("r2_h2d", C.c_double), ("r2_d2h", C.c_double)]
 
 
 SINK = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
@@ -83,6 +88,8 @@ def load() -> C.CDLL:
         lib.hlc_xmatch_stream.restype = C.c_int
         lib.hlc_xmatch_stream.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, SINK, vp,
                                           C.POINTER(hlc_opts)]
+        lib.hlc_transfer_model.restype = C.c_int
+        lib.hlc_transfer_model.argtypes = [C.POINTER(hlc_transfer)]
         lib.hlc_strerror.restype = C.c_char_p
         lib.hlc_strerror.argtypes = [C.c_int]
         lib.hlc_last_stats.restype = C.c_int
@@ -289,6 +296,15 @@ def hlc_xmatch_batch(jobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep, job_pai
     st = load().hlc_xmatch_batch(arr, len(jobs), _ptr(a_ra), _ptr(a_dec), _ptr(b_ra), _ptr(b_dec),
                                  _ptr(out_pairs), _ptr(out_sep), _ptr(job_pair_count), C.byref(o))
     return st, n.value
+
+
+def transfer_model() -> dict:
+    """The eq. (5) host<->device model fitted on this device: alpha (s), beta (s/byte)."""
+    t = hlc_transfer()
+    st = load().hlc_transfer_model(C.byref(t))
+    if st != HLC_OK:
+        raise HLCError(st, "hlc_transfer_model")
+    return {k: getattr(t, k) for k, _ in hlc_transfer._fields_}
 
 
 def last_stats() -> dict:

@@ -1211,6 +1211,90 @@ struct StreamCall {
   }
 };
 
+// ---------------------------------------------------------------------------
+// eq. (5) transfer model: T(d) = alpha + beta d, fitted to timed copies
+// ---------------------------------------------------------------------------
+struct TransferModel {
+  bool have = false;
+  hlc_transfer m{};
+};
+TransferModel g_tm[MAX_DEVICES];
+
+void fit_line(const std::vector<double>& x, const std::vector<double>& y, double& a, double& b, double& r2) {
+  const double n = (double)x.size();
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (size_t i = 0; i < x.size(); ++i) {
+    sx += x[i];
+    sy += y[i];
+    sxx += x[i] * x[i];
+    sxy += x[i] * y[i];
+  }
+  b = (n * sxy - sx * sy) / (n * sxx - sx * sx);
+  a = (sy - b * sx) / n;
+  double my = sy / n, ss_tot = 0, ss_res = 0;
+  for (size_t i = 0; i < x.size(); ++i) {
+    const double f = a + b * x[i];
+    ss_res += (y[i] - f) * (y[i] - f);
+    ss_tot += (y[i] - my) * (y[i] - my);
+  }
+  r2 = ss_tot > 0 ? 1.0 - ss_res / ss_tot : 1.0;
+}
+
+int measure_transfer(int dev_id, hlc_transfer* out) {
+  TransferModel& T = g_tm[dev_id];
+  if (T.have) {
+    *out = T.m;
+    return HLC_OK;
+  }
+  const size_t maxb = size_t(1) << 26;
+  void *h = nullptr, *d = nullptr;
+  if (alloc_fails(maxb)) return HLC_E_NOMEM;
+  HLC_TRY(hipHostMalloc(&h, maxb, hipHostMallocDefault));
+  if (hipMalloc(&d, maxb) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(h);
+    return HLC_E_NOMEM;
+  }
+  std::memset(h, 1, maxb);
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  int st = HLC_OK;
+  if (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    st = HLC_E_DEVICE;
+  } else {
+    std::vector<double> xs, yh, yd;
+    for (int k = 0; k <= 26; k += 2) {
+      const size_t bytes = size_t(1) << k;
+      for (int dir = 0; dir < 2; ++dir) {
+        double best = 1e30;
+        for (int rep = 0; rep < 5; ++rep) {  // best of five: transient noise only adds time
+          (void)hipEventRecord(e0, s);
+          if (dir == 0) (void)hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
+          else (void)hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          best = std::min(best, (double)ms * 1e-3);
+        }
+        (dir == 0 ? yh : yd).push_back(best);
+      }
+      xs.push_back((double)bytes);
+    }
+    fit_line(xs, yh, T.m.alpha_h2d, T.m.beta_h2d, T.m.r2_h2d);
+    fit_line(xs, yd, T.m.alpha_d2h, T.m.beta_d2h, T.m.r2_d2h);
+    T.have = true;
+    *out = T.m;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+  }
+  (void)hipFree(d);
+  (void)hipHostFree(h);
+  return st;
+}
+
 constexpr int32_t STREAM_DEC_BINS = 8192;
 constexpr int64_t STREAM_SLAB = int64_t(1) << 25;  // sources per host->device copy
 
@@ -1278,8 +1362,22 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
   if (dev->cnt_host->err) return HLC_E_INVAL;
 
   // 2. Dec chunks: consecutive histogram bins holding <= CHUNK A sources
-  //    (a single dense bin may exceed it)
-  const int64_t CHUNK = int64_t(1) << 23;
+  //    (a single dense bin may exceed it). With per-chunk fixed cost
+  //    s = alpha_h2d + alpha_d2h + launch overhead (about 25 launches of
+  //    ~5 us and two synchronisations) and whole-job time W (inputs over the
+  //    link, one pair per A source back, compute at ~2e9 sources/s), about
+  //    sqrt(W / s) chunks balance the fixed costs against fill and drain.
+  int dev_id = 0;
+  HLC_TRY(hipGetDevice(&dev_id));
+  hlc_transfer tm{};
+  int64_t CHUNK = int64_t(1) << 23;
+  if (measure_transfer(dev_id, &tm) == HLC_OK && tm.beta_h2d > 0 && tm.beta_d2h > 0) {
+    const double s_fix = std::max(tm.alpha_h2d, 0.0) + std::max(tm.alpha_d2h, 0.0) + 2.0e-4;
+    const double W = tm.beta_h2d * 16.0 * (double)(na + nb) + tm.beta_d2h * 16.0 * (double)na +
+                     (double)(na + nb) / 2.0e9;
+    const double k = std::sqrt(W / s_fix);
+    CHUNK = (int64_t)std::min(std::max((double)na / std::max(k, 1.0), 1.0e6), 3.2e7);
+  }
   std::vector<int32_t> chunk_of_bin(STREAM_DEC_BINS);
   std::vector<double> edges{-90.0};
   int64_t acc = 0;
@@ -1420,6 +1518,18 @@ int hlc_xmatch_stream(const double* a_ra_host, const double* a_dec_host, int64_t
     return stream_impl(a_ra_host, a_dec_host, na, b_ra_host, b_dec_host, nb, r_arcsec, sink, user, opts);
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
+  } catch (...) {
+    return HLC_E_DEVICE;
+  }
+}
+
+int hlc_transfer_model(hlc_transfer* out) {
+  if (!out) return HLC_E_INVAL;
+  try {
+    Device* dev = nullptr;
+    int dev_id = 0;
+    HLC_CHECK(get_device(&dev, &dev_id));
+    return measure_transfer(dev_id, out);
   } catch (...) {
     return HLC_E_DEVICE;
   }

@@ -84,3 +84,14 @@ def test_stream_large_400M_x_100M_sampled(hlc):
     assert np.max(np.abs(sep[mine][o] - ref.sep[ro])) <= 1e-9
     # counterpart + chance expectation of the recipe (Appendix-style arithmetic)
     assert 1.0e8 < len(pairs) < 1.3e8
+
+
+def test_transfer_model_fit(hlc):
+    """Eq. (5): T(d) = alpha + beta d fits the timed pinned copies."""
+    m = hlc.transfer_model()
+    print("transfer model", m, flush=True)
+    for d in ("h2d", "d2h"):
+        beta = m[f"beta_{d}"]
+        assert 1.0 / 400e9 < beta < 1.0 / 1e9, (d, beta)   # 1 .. 400 GB/s
+        assert -1e-4 < m[f"alpha_{d}"] < 1e-3, (d, m[f"alpha_{d}"])
+        assert m[f"r2_{d}"] > 0.95

@@ -58,6 +58,11 @@ def _load():
         lib.oracle_xmatch_radii.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int, C.c_int,
                                             C.POINTER(C.c_int)]
+        lib.oracle_hp_nest.restype = C.c_int64
+        lib.oracle_hp_nest.argtypes = [C.c_int, C.c_double, C.c_double]
+        lib.oracle_quad_direction.restype = C.c_void_p
+        lib.oracle_quad_direction.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                              C.c_int64, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int)]
         lib.oracle_brute.restype = C.c_void_p
         lib.oracle_brute.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_int64, C.c_double, C.c_int, C.POINTER(C.c_int)]
@@ -146,6 +151,25 @@ def xmatch_radii(a_ra, a_dec, a_err, b_ra, b_dec, b_err, k: float = 3.0, nthread
     h = lib.oracle_xmatch_radii(a_ra.ctypes.data, a_dec.ctypes.data, a_err.ctypes.data, len(a_ra),
                                 b_ra.ctypes.data, b_dec.ctypes.data, b_err.ctypes.data, len(b_ra), float(k),
                                 int(nthreads), 1 if brute else 0, C.byref(st))
+    if st.value != 0 or not h:
+        raise OracleError("invalid input")
+    return _collect(lib, h, t0)
+
+
+def hp_nest(order: int, ra: float, dec: float) -> int:
+    """HEALPix nested pixel index at Nside = 2**order."""
+    return int(_load().oracle_hp_nest(int(order), float(ra), float(dec)))
+
+
+def quad_direction(a_ra, a_dec, b_ra, b_dec, r_arcsec: float, order: int, nthreads: int = 0) -> Result:
+    """Pairs found by the emulated paper partition (HEALPix + quad-direction copies)."""
+    lib = _load()
+    a_ra, a_dec, b_ra, b_dec = map(_f64, (a_ra, a_dec, b_ra, b_dec))
+    st = C.c_int(0)
+    t0 = time.perf_counter()
+    h = lib.oracle_quad_direction(a_ra.ctypes.data, a_dec.ctypes.data, len(a_ra), b_ra.ctypes.data,
+                                  b_dec.ctypes.data, len(b_ra), float(r_arcsec), int(order), int(nthreads),
+                                  C.byref(st))
     if st.value != 0 or not h:
         raise OracleError("invalid input")
     return _collect(lib, h, t0)

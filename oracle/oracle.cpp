@@ -423,6 +423,80 @@ oracle_result* oracle_xmatch_radii(const double* a_ra, const double* a_dec, cons
   return res;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's partition, emulated (section 3.2, Algorithm 1; section 4.2):
+// every record is indexed by its HEALPix nested pixel at `order` and, in
+// addition, by the pixels of the four positions shifted by +-R in RA and in
+// Dec (R = the match radius in degrees, as Alg. 1 adds the error radius to
+// the coordinates; RA shifts wrap around 360, Dec shifts stop at the poles).
+// Records are compared only within a shared pixel; the decision is the exact
+// one above, so the pairs missed are the partition's completeness loss.
+// ---------------------------------------------------------------------------
+
+// HEALPix nested pixel of (ra, dec) at Nside = 2^order, from the definitions
+// of the HEALPix pixelisation (twelve base faces; equatorial zone |z| <= 2/3
+// cut by two families of lines, polar caps by square-root scaled lines; the
+// nested index interleaves the bits of the two in-face coordinates).
+int64_t hp_nest(int order, double ra, double dec) {
+  const int64_t ns = int64_t(1) << order;
+  const double z = std::sin(dec * K64);
+  const double za = std::fabs(z);
+  double tt = ra / 90.0;  // phi / (pi/2), in [0, 4)
+  tt = std::fmod(tt, 4.0);
+  if (tt < 0) tt += 4.0;
+  int64_t face, ix, iy;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = ns * (0.5 + tt), t2 = ns * (z * 0.75);
+    const int64_t jp = (int64_t)(t1 - t2), jm = (int64_t)(t1 + t2);
+    const int64_t ifp = jp >> order, ifm = jm >> order;
+    face = (ifp == ifm) ? (ifp | 4) : (ifp < ifm ? ifp : ifm + 8);
+    ix = jm & (ns - 1);
+    iy = ns - (jp & (ns - 1)) - 1;
+  } else {
+    int64_t ntt = (int64_t)tt;
+    if (ntt > 3) ntt = 3;
+    const double tp = tt - (double)ntt;
+    // 1 - |z| = 2 sin^2(colatitude / 2), without cancellation
+    const double sh = std::sin(0.5 * (90.0 - std::fabs(dec)) * K64);
+    const double tmp = ns * std::sqrt(6.0) * sh;
+    int64_t jp = (int64_t)(tp * tmp), jm = (int64_t)((1.0 - tp) * tmp);
+    jp = std::min(jp, ns - 1);
+    jm = std::min(jm, ns - 1);
+    if (z >= 0) {
+      face = ntt;
+      ix = ns - jm - 1;
+      iy = ns - jp - 1;
+    } else {
+      face = ntt + 8;
+      ix = jp;
+      iy = jm;
+    }
+  }
+  int64_t ipf = 0;
+  for (int b = 0; b < order; ++b) ipf |= ((ix >> b) & 1) << (2 * b) | ((iy >> b) & 1) << (2 * b + 1);
+  return face * ns * ns + ipf;
+}
+
+// The distinct pixels of a record: its own and those of the four shifts.
+int hp_quad(int order, double ra, double dec, double R, int64_t out[5]) {
+  auto fold = [](double a) {
+    a = std::fmod(a, 360.0);
+    return a < 0 ? a + 360.0 : a;
+  };
+  int n = 0;
+  auto put = [&](int64_t p) {
+    for (int k = 0; k < n; ++k)
+      if (out[k] == p) return;
+    out[n++] = p;
+  };
+  put(hp_nest(order, ra, dec));
+  put(hp_nest(order, fold(ra + R), dec));
+  put(hp_nest(order, fold(ra - R), dec));
+  put(hp_nest(order, ra, std::min(dec + R, 90.0)));
+  put(hp_nest(order, ra, std::max(dec - R, -90.0)));
+  return n;
+}
+
 // All m*n pairs, same decision. For small inputs only.
 oracle_result* oracle_brute(const double* a_ra, const double* a_dec, int64_t na,
                             const double* b_ra, const double* b_dec, int64_t nb,
@@ -458,6 +532,64 @@ oracle_result* oracle_brute(const double* a_ra, const double* a_dec, int64_t na,
     res->st.ties += s.ties;
   }
   res->st.candidates = na * nb;
+  finish(res, parts, true);
+  return res;
+}
+
+int64_t oracle_hp_nest(int order, double ra, double dec) {
+  if (order < 0 || order > 13 || !valid_pos(ra, dec)) return -1;
+  return hp_nest(order, ra, dec);
+}
+
+// Pairs the emulated paper partition finds (each once), exact decisions.
+oracle_result* oracle_quad_direction(const double* a_ra, const double* a_dec, int64_t na,
+                                     const double* b_ra, const double* b_dec, int64_t nb,
+                                     double r_arcsec, int order, int nthreads, int* status) {
+  *status = -1;
+  if (na < 0 || nb < 0 || order < 0 || order > 13) return nullptr;
+  if (!(r_arcsec > 0.0) || !(r_arcsec <= 3600.0)) return nullptr;
+  int nt = resolve_threads(nthreads);
+  omp_set_num_threads(nt);
+  if (!check_inputs(a_ra, a_dec, na) || !check_inputs(b_ra, b_dec, nb)) return nullptr;
+  auto* res = new oracle_result();
+  *status = 0;
+  const double R = r_arcsec / 3600.0;
+  // (pixel, index) lists of B, sorted by pixel
+  std::vector<std::pair<int64_t, uint32_t>> Bp;
+  for (int64_t j = 0; j < nb; ++j) {
+    int64_t px[5];
+    int n = hp_quad(order, b_ra[j], b_dec[j], R, px);
+    for (int k = 0; k < n; ++k) Bp.emplace_back(px[k], (uint32_t)j);
+  }
+  __gnu_parallel::sort(Bp.begin(), Bp.end());
+  Thresh t = make_thresh(r_arcsec);
+  std::vector<std::vector<Hit>> parts(nt);
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = omp_get_thread_num();
+#pragma omp for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < na; ++i) {
+      int64_t pa[5];
+      int n = hp_quad(order, a_ra[i], a_dec[i], R, pa);
+      for (int k = 0; k < n; ++k) {
+        auto it = std::lower_bound(Bp.begin(), Bp.end(), std::make_pair(pa[k], (uint32_t)0));
+        for (; it != Bp.end() && it->first == pa[k]; ++it) {
+          const uint32_t j = it->second;
+          // count a pair once: in the smallest pixel the two records share
+          int64_t pb[5];
+          int m = hp_quad(order, b_ra[j], b_dec[j], R, pb);
+          int64_t first = INT64_MAX;
+          for (int u = 0; u < n; ++u)
+            for (int v = 0; v < m; ++v)
+              if (pa[u] == pb[v]) first = std::min(first, pa[u]);
+          if (first != pa[k]) continue;
+          double sep;
+          int o = decide(a_ra[i], a_dec[i], cos_dec64(a_dec[i]), b_ra[j], b_dec[j], cos_dec64(b_dec[j]), t, &sep);
+          if (o == IN_FP64 || o == IN_QUAD || o == IN_TIE) parts[tid].push_back(Hit{(uint32_t)i, j, sep});
+        }
+      }
+    }
+  }
   finish(res, parts, true);
   return res;
 }

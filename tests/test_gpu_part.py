@@ -19,7 +19,7 @@ def hlc():
     return m
 
 
-def _run(hlc, A, B, r, prec, cap=400_000):
+def _run(hlc, A, B, r, prec, cap):
     import torch
     out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
     sep = torch.empty(cap, dtype=torch.float64, device="cuda")
@@ -44,12 +44,14 @@ def test_parts_reuse_both_roles(hlc, prec):
     st, PB = hlc.hlc_partition(to_dev(b_ra), to_dev(b_dec), 3.0)
     assert st == hlc.HLC_OK
     for r in (3.0, 1.0, 0.25):
-        keys, sep = _run(hlc, PA, PB, r, prec)
-        assert_same(keys, sep, oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r), label=f"A-B r={r}")
-        keys, sep = _run(hlc, PB, PA, r, prec)
-        assert_same(keys, sep, oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r), label=f"B-A r={r}")
-    keys, sep = _run(hlc, PA, PA, 1.0, prec)
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        keys, sep = _run(hlc, PA, PB, r, prec, len(ref) + 100)
+        assert_same(keys, sep, ref, label=f"A-B r={r}")
+        ref = oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r)
+        keys, sep = _run(hlc, PB, PA, r, prec, len(ref) + 100)
+        assert_same(keys, sep, ref, label=f"B-A r={r}")
     ref = oracle.xmatch(a_ra, a_dec, a_ra, a_dec, 1.0)
+    keys, sep = _run(hlc, PA, PA, 1.0, prec, len(ref) + 100)
     assert_same(keys, sep, ref, label="A-A")
     assert np.all(np.isin((np.arange(len(a_ra), dtype=np.uint64) << np.uint64(32)) |
                           np.arange(len(a_ra), dtype=np.uint64), keys))

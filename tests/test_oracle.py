@@ -340,3 +340,90 @@ def test_radii_invalid_and_zero_errors():
     dec = np.array([5.0, 5.0, 5.0])
     res = oracle.xmatch_radii(ra, dec, np.zeros(3), ra[:1], dec[:1], np.zeros(1), 3.0)
     assert sorted(res.a.tolist()) == [0, 1]
+
+
+# ---------------------------------------------------------------------------
+# the paper's partition, emulated: HEALPix nested pixels + quad-direction copies
+# ---------------------------------------------------------------------------
+def test_healpix_base_faces():
+    """Nside = 1: the twelve base pixels are centred at z = 2/3, 0, -2/3 and phi = 45 + 90k / 90k."""
+    d = math.degrees(math.asin(2.0 / 3.0))
+    assert [oracle.hp_nest(0, 45 + 90 * k, d) for k in range(4)] == [0, 1, 2, 3]
+    assert [oracle.hp_nest(0, (90 * k) % 360, 0.0) for k in range(4)] == [4, 5, 6, 7]
+    assert [oracle.hp_nest(0, 45 + 90 * k, -d) for k in range(4)] == [8, 9, 10, 11]
+    assert oracle.hp_nest(0, 10.0, 90.0) == 0 and oracle.hp_nest(0, 10.0, -90.0) == 8
+
+
+def test_healpix_nesting_and_range():
+    """Nested scheme: the parent of a pixel at order k+1 is its index >> 2 at order k."""
+    g = synth.rng(930, 0)
+    ra, dec = synth.uniform_sphere(g, 3000)
+    for k in range(0, 13):
+        for i in range(0, 3000, 7):
+            p1 = oracle.hp_nest(k + 1, ra[i], dec[i])
+            p0 = oracle.hp_nest(k, ra[i], dec[i])
+            assert p1 >> 2 == p0
+            assert 0 <= p1 < 12 * 4 ** (k + 1)
+
+
+def test_healpix_equal_areas():
+    """Uniform points fill the 192 pixels of order 2 equally (chi-square, 191 dof)."""
+    g = synth.rng(931, 0)
+    n = 96000
+    ra, dec = synth.uniform_sphere(g, n)
+    counts = np.bincount([oracle.hp_nest(2, ra[i], dec[i]) for i in range(n)], minlength=192)
+    e = n / 192
+    chi2 = float(((counts - e) ** 2 / e).sum())
+    assert chi2 < 191 + 5 * math.sqrt(2 * 191)
+
+
+def _alg1_plain(a_ra, a_dec, b_ra, b_dec, r, order):
+    """Algorithm 1 and the per-pixel join written out with Python dicts (tiny inputs)."""
+    R = r / 3600.0
+
+    def pix(ra, dec):
+        out = []
+        for (x, y) in ((ra, dec), ((ra + R) % 360.0, dec), ((ra - R) % 360.0, dec),
+                       (ra, min(dec + R, 90.0)), (ra, max(dec - R, -90.0))):
+            p = oracle.hp_nest(order, x, y)
+            if p not in out:
+                out.append(p)
+        return out
+
+    PB = {}
+    pb_all = [pix(b_ra[j], b_dec[j]) for j in range(len(b_ra))]
+    for j, ps in enumerate(pb_all):
+        for p in ps:
+            PB.setdefault(p, []).append(j)
+    found = set()
+    for i in range(len(a_ra)):
+        for p in pix(a_ra[i], a_dec[i]):
+            for j in PB.get(p, []):
+                code, _ = oracle.pair(a_ra[i], a_dec[i], b_ra[j], b_dec[j], r)
+                if code in (oracle.IN_FP64, oracle.IN_QUAD, oracle.IN_TIE):
+                    found.add((i << 32) | j)
+    return np.array(sorted(found), dtype=np.uint64)
+
+
+@pytest.mark.parametrize("order", [6, 9, 12])
+def test_quad_direction_against_plain_algorithm(order):
+    for kind in ("dense", "pole", "seam"):
+        a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 250, 8, 2.0)
+        q = oracle.quad_direction(a_ra, a_dec, b_ra, b_dec, 2.0, order)
+        assert np.array_equal(q.keys(), _alg1_plain(a_ra, a_dec, b_ra, b_dec, 2.0, order))
+
+
+def test_quad_direction_subset_and_loss():
+    """The emulated scheme finds only true pairs; at high Dec, where a shift of R
+    in RA covers only R cos(Dec) on the sky, it loses some, more at finer orders."""
+    g = synth.rng(932, 0)
+    a_ra, a_dec = synth.uniform_patch(g, 30000, 20.0, 21.5, 88.0, 88.3)
+    b_ra, b_dec = synth.uniform_patch(g, 30000, 20.0, 21.5, 88.0, 88.3)
+    r = 3.0
+    exact = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+    lost = []
+    for order in (8, 10, 13):
+        q = oracle.quad_direction(a_ra, a_dec, b_ra, b_dec, r, order)
+        assert np.all(np.isin(q.keys(), exact.keys()))
+        lost.append(len(exact) - len(q))
+    assert lost[0] < lost[1] < lost[2] and 0 < lost[2] < len(exact) // 100

@@ -134,6 +134,19 @@ int hlc_xmatch_radii(const double *a_ra, const double *a_dec, const double *a_er
                      double k_sigma, hlc_pair *out_pairs, double *out_sep_arcsec,
                      const hlc_opts *opts);
 
+/* The paper's own partition, emulated for comparison (section 3.2,
+ * Algorithm 1; section 4.2; Table 4): each record of A and B is indexed by its
+ * HEALPix nested pixel at `order` (0..13) and by the pixels of its four
+ * positions shifted by +-r in RA and in Dec (the quad-direction strategy;
+ * RA wraps, Dec stops at the poles); records are compared only within a
+ * shared pixel, with the same exact decision as hlc_xmatch, and each pair is
+ * reported once. The result is a subset of hlc_xmatch's: the pairs it lacks
+ * are the scheme's completeness loss. na, nb < 2^28. Arguments, outputs and
+ * errors otherwise as hlc_xmatch (the filter is FP64; HLC_SELF unsupported). */
+int hlc_xmatch_quad(const double *a_ra, const double *a_dec, int64_t na, const double *b_ra,
+                    const double *b_dec, int64_t nb, double r_arcsec, int32_t order,
+                    hlc_pair *out_pairs, double *out_sep_arcsec, const hlc_opts *opts);
+
 /* Reusable device index of one catalogue (section 4.2's first-level
  * partition: positions grouped by Dec zone, then RA). An index built for
  * radius r can serve as either side of hlc_xmatch_part at any radius <= r

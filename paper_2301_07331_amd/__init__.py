@@ -17,7 +17,7 @@ HLC_OK, HLC_E_INVAL, HLC_E_NOMEM, HLC_E_OVERFLOW, HLC_E_DEVICE, HLC_E_UNSUPPORTE
 HLC_FP32_RECHECK, HLC_FP64 = 0, 1
 HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF = 0x1, 0x2, 0x4, 0x8
 
-EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
+EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
            "hlc_xmatch_stream", "hlc_transfer_model", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
 
 
@@ -76,6 +76,9 @@ def load() -> C.CDLL:
         lib.hlc_xmatch_radii.restype = C.c_int
         lib.hlc_xmatch_radii.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp, vp,
                                          C.POINTER(hlc_opts)]
+        lib.hlc_xmatch_quad.restype = C.c_int
+        lib.hlc_xmatch_quad.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, C.c_int32, vp, vp,
+                                        C.POINTER(hlc_opts)]
         lib.hlc_partition.restype = C.c_int
         lib.hlc_partition.argtypes = [vp, vp, i64, C.c_double, C.POINTER(hlc_opts), C.POINTER(vp)]
         lib.hlc_part_free.restype = None
@@ -195,6 +198,18 @@ def hlc_xmatch_radii(a_ra, a_dec, a_err, b_ra, b_dec, b_err, k_sigma, out_pairs,
     st = load().hlc_xmatch_radii(_ptr(a_ra), _ptr(a_dec), _ptr(a_err), a_ra.numel(), _ptr(b_ra),
                                  _ptr(b_dec), _ptr(b_err), b_ra.numel(), float(k_sigma), _ptr(out_pairs),
                                  _ptr(out_sep), C.byref(o))
+    return st, n.value
+
+
+def hlc_xmatch_quad(a_ra, a_dec, b_ra, b_dec, r_arcsec, order, out_pairs, out_sep, *, capacity=None,
+                    stream=None, flags=0):
+    """The paper's HEALPix + quad-direction partition, emulated. Returns (status, n_pairs)."""
+    _check_coords(a_ra, a_dec, b_ra, b_dec)
+    if capacity is None:
+        capacity = 0 if out_pairs is None else out_pairs.shape[0]
+    o, n, tu = make_opts(HLC_FP64, capacity, stream, flags, None)
+    st = load().hlc_xmatch_quad(_ptr(a_ra), _ptr(a_dec), a_ra.numel(), _ptr(b_ra), _ptr(b_dec), b_ra.numel(),
+                                float(r_arcsec), int(order), _ptr(out_pairs), _ptr(out_sep), C.byref(o))
     return st, n.value
 
 

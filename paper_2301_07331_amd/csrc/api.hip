@@ -307,6 +307,7 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.a_err = rad.a_err;
   ma.b_err = rad.b_err;
   ma.k_sigma = rad.k;
+  ma.hp_order = -1;
   OutArgs oa{};
   oa.pairs = reinterpret_cast<uint2*>(out_pairs);
   oa.sep = out_sep;
@@ -580,6 +581,111 @@ int hlc_xmatch_radii(const double* a_ra, const double* a_dec, const double* a_er
     rmax = std::max(rmax, 1e-6);
     return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, rmax, out_pairs, out_sep_arcsec, opts,
                        Radii{a_err, b_err, k_sigma});
+  } catch (const std::bad_alloc&) {
+    return HLC_E_NOMEM;
+  } catch (...) {
+    return HLC_E_DEVICE;
+  }
+}
+
+int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
+                    const double* b_dec, int64_t nb, double r_arcsec, int32_t order, hlc_pair* out_pairs,
+                    double* out_sep_arcsec, const hlc_opts* opts) {
+  int st = check_common(r_arcsec, na, nb, opts);
+  if (st) return st;
+  if (order < 0 || order > 13) return HLC_E_INVAL;
+  if (na >= (int64_t(1) << 28) || nb >= (int64_t(1) << 28)) return HLC_E_INVAL;  // 5 entries each
+  if ((na > 0 && (!a_ra || !a_dec)) || (nb > 0 && (!b_ra || !b_dec))) return HLC_E_INVAL;
+  if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
+    return HLC_E_INVAL;
+  if (opts->flags & HLC_SELF) return HLC_E_UNSUPPORTED;
+  try {
+    if (na == 0 || nb == 0) return validate_only(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, opts);
+    Device* dev = nullptr;
+    HLC_CHECK(get_device(&dev));
+    hipStream_t s = (hipStream_t)opts->stream;
+    const uint32_t capA = 5u * (uint32_t)na, capB = 5u * (uint32_t)nb;
+    uint64_t band_cap = (1u << 20) + (uint64_t)(capA + capB) / 64;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      Side A, B;
+      SortScratch sc;
+      MatchWs w;
+      Geom g{};
+      set_radius(g, r_arcsec);
+      g.rb = 0;  // keys are pixels: a candidate must share the A entry's pixel
+      g.nz = 1;
+      auto lay = [&](Carve& c) {
+        carve_side(c, A, capA, true, true);
+        carve_side(c, B, capB, true, true);
+        carve_sort(c, sc, std::max(capA, capB));
+        carve_match_ws(c, w, capA, g, band_cap, false);
+      };
+      Carve sz{nullptr};
+      lay(sz);
+      HLC_CHECK(ensure_ws(*dev, sz.off + 256));
+      Carve c{(char*)dev->ws};
+      lay(c);
+      launch_zero_counters(dev->cnt, s);
+      const double R = r_arcsec / 3600.0;
+      launch_hp_keygen(a_ra, a_dec, (uint32_t)na, order, R, 1u, A.keys, A.vals, &dev->cnt->aux[0], dev->cnt, s);
+      launch_hp_keygen(b_ra, b_dec, (uint32_t)nb, order, R, 2u, B.keys, B.vals, &dev->cnt->aux[1], dev->cnt, s);
+      A.cnt = DevCount{0, capA, &dev->cnt->aux[0]};
+      B.cnt = DevCount{0, capB, &dev->cnt->aux[1]};
+      A.ra = a_ra; A.dec = a_dec; B.ra = b_ra; B.dec = b_dec;
+      const int kb = 2 * order + 4;  // 12 * 4^order < 2^(2 order + 4)
+      radix_sort(A.keys, A.vals, A.cnt, kb, sc, s);
+      radix_sort(B.keys, B.vals, B.cnt, kb, sc, s);
+      launch_layout64(A.vals, A.cnt, a_ra, a_dec, A.r64, s);
+      launch_layout64(B.vals, B.cnt, b_ra, b_dec, B.r64, s);
+      launch_radec_gather(A.vals, A.cnt, a_ra, a_dec, A.radec, s);
+      launch_radec_gather(B.vals, B.cnt, b_ra, b_dec, B.radec, s);
+      launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, w.lb, s);
+      launch_equal_ranges(A.keys, A.cnt, w.lb, B.keys, B.cnt, w.ranges, s);
+      const Thresholds th = thresholds(r_arcsec);
+      MatchArgs ma{};
+      ma.ranges = w.ranges;
+      ma.na = A.cnt;
+      ma.recA64 = A.r64;
+      ma.recB64 = B.r64;
+      ma.t_lo64 = th.t_lo64;
+      ma.t_hi64 = th.t_hi64;
+      ma.radecA = A.radec;
+      ma.radecB = B.radec;
+      ma.keysA = A.keys;
+      ma.keysB = B.keys;
+      ma.geom = g;
+      ma.H_lo = th.H_lo;
+      ma.H_hi = th.H_hi;
+      ma.hp_order = order;
+      ma.hp_R = R;
+      OutArgs oa{};
+      oa.pairs = reinterpret_cast<uint2*>(out_pairs);
+      oa.sep = (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec;
+      oa.cap = (uint64_t)opts->capacity;
+      oa.band = w.band;
+      oa.band_cap = band_cap;
+      oa.cnt = dev->cnt;
+      launch_match64(ma, oa, s);
+      launch_certify(a_ra, a_dec, b_ra, b_dec, r_arcsec, th.H_lo, th.H_hi, Radii{nullptr, nullptr, 0.0}, oa, s);
+      HLC_CHECK(read_counters(*dev, s, false));
+      const Counters& h = *dev->cnt_host;
+      if (h.err) return HLC_E_INVAL;
+      if (h.n_band > band_cap) {
+        band_cap = h.n_band + h.n_band / 4 + 1024;
+        continue;
+      }
+      std::memset(&g_stats, 0, sizeof(g_stats));
+      g_stats.na = na;
+      g_stats.nb = nb;
+      g_stats.nb_halo = (int64_t)h.aux[1];  // B entries (records with their copies)
+      g_stats.n_pairs = (int64_t)h.n_pairs;
+      g_stats.n_candidates = (int64_t)h.n_cand;
+      g_stats.n_band = (int64_t)h.n_band;
+      g_stats.n_ties = (int64_t)h.n_ties;
+      *opts->n_pairs = (int64_t)h.n_pairs;
+      return h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK;
+    }
+    return HLC_E_NOMEM;
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {

@@ -70,7 +70,7 @@ struct Counters {
   unsigned long long n_ties;      // decided in double-double
   unsigned int err;               // bit 0: bad coordinate in A, bit 1: in B
   unsigned int queue;             // work-queue head of persistent kernels
-  unsigned long long pad2_[2];
+  unsigned long long aux[2];      // entry counts of multi-entry keygens (A, B)
 };
 
 struct Rec64 {      // FP64 working record (32 B)
@@ -155,6 +155,82 @@ __device__ inline double haversine64(double ra1, double dec1, double ra2, double
   sincos_deg(0.5 * (dec1 - dec2), &s1, &c1);
   sincos_deg(0.5 * dra_fold(ra1, ra2), &s2, &c2);
   return s1 * s1 + cos_deg_abs(dec1) * cos_deg_abs(dec2) * (s2 * s2);
+}
+
+// ---------------------------------------------------------------------------
+// HEALPix nested pixel index at Nside = 2^order (the paper's first-level
+// partition, section 4.2), from the definitions of the pixelisation: twelve
+// base faces; in the equatorial zone |z| <= 2/3 the in-face coordinates come
+// from two families of straight lines in (phi, z), in the polar caps from
+// lines scaled by sqrt(1 - |z|); the nested index interleaves their bits.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t hp_spread(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__device__ inline uint32_t hp_nest(int order, double ra, double dec) {
+  const int32_t ns = 1 << order;
+  double z, c;
+  sincos_deg(dec, &z, &c);
+  const double za = fabs(z);
+  double tt = ra * (1.0 / 90.0);
+  if (tt >= 4.0) tt -= 4.0;
+  if (tt < 0.0) tt += 4.0;
+  int32_t face, ix, iy;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = ns * (0.5 + tt), t2 = ns * (z * 0.75);
+    const int32_t jp = (int32_t)(t1 - t2), jm = (int32_t)(t1 + t2);
+    const int32_t ifp = jp >> order, ifm = jm >> order;
+    face = (ifp == ifm) ? (ifp | 4) : (ifp < ifm ? ifp : ifm + 8);
+    ix = jm & (ns - 1);
+    iy = ns - (jp & (ns - 1)) - 1;
+  } else {
+    int32_t ntt = (int32_t)tt;
+    if (ntt > 3) ntt = 3;
+    const double tp = tt - (double)ntt;
+    double sh, ch;  // 1 - |z| = 2 sin^2(colatitude / 2)
+    sincos_deg(0.5 * (90.0 - fabs(dec)), &sh, &ch);
+    const double tmp = ns * 2.449489742783178 * sh;  // sqrt(6)
+    int32_t jp = (int32_t)(tp * tmp), jm = (int32_t)((1.0 - tp) * tmp);
+    jp = min(jp, ns - 1);
+    jm = min(jm, ns - 1);
+    if (z >= 0.0) {
+      face = ntt;
+      ix = ns - jm - 1;
+      iy = ns - jp - 1;
+    } else {
+      face = ntt + 8;
+      ix = jp;
+      iy = jm;
+    }
+  }
+  return (uint32_t)face * (uint32_t)ns * (uint32_t)ns + (hp_spread((uint32_t)ix) | (hp_spread((uint32_t)iy) << 1));
+}
+
+// Distinct pixels of a record under the quad-direction strategy (section
+// 3.2, Algorithm 1 read with its Dec-minus line as dec - R): its own pixel
+// and those of (ra +- R, dec) and (ra, dec +- R); RA wraps, Dec stops at +-90.
+__device__ inline int hp_quad(int order, double ra, double dec, double R, uint32_t out[5]) {
+  int n = 0;
+  auto put = [&](uint32_t p) {
+    for (int k = 0; k < n; ++k)
+      if (out[k] == p) return;
+    out[n++] = p;
+  };
+  double rp = ra + R, rm = ra - R;
+  if (rp >= 360.0) rp -= 360.0;
+  if (rm < 0.0) rm += 360.0;
+  put(hp_nest(order, ra, dec));
+  put(hp_nest(order, rp, dec));
+  put(hp_nest(order, rm, dec));
+  put(hp_nest(order, ra, fmin(dec + R, 90.0)));
+  put(hp_nest(order, ra, fmax(dec - R, -90.0)));
+  return n;
 }
 
 // ---------------------------------------------------------------------------

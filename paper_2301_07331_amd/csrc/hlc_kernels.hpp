@@ -82,6 +82,10 @@ struct MatchArgs {
   const double* a_err;
   const double* b_err;
   double k_sigma;
+  // paper-scheme emulation (HEALPix order >= 0): keys are pixels; a pair is
+  // kept in the smallest pixel its two records share
+  int hp_order;
+  double hp_R;
 };
 
 // Error radii of one call (nullptr a_err: a single radius).
@@ -102,6 +106,16 @@ void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,
 // negative or non-finite error
 void launch_err_max(const double* err, uint32_t n, unsigned long long* out_code, Counters* cnt,
                     hipStream_t s);
+
+// paper-scheme emulation: up to five (pixel, index) entries per record,
+// appended after the counter *count (device)
+void launch_hp_keygen(const double* ra, const double* dec, uint32_t n, int order, double R, uint32_t err_bit,
+                      uint32_t* keys, uint32_t* vals, unsigned long long* count, Counters* cnt, hipStream_t s);
+void launch_radec_gather(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
+                         double2* radec, hipStream_t s);
+// per group of 16 A entries: B ranges of equal keys
+void launch_equal_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
+                         const DevCount& nb, GroupRanges* out, hipStream_t s);
 
 // ---- stream.hip ------------------------------------------------------------
 void launch_dec_hist(const double* ra, const double* dec, uint32_t n, int32_t nbins, uint32_t* hist,

@@ -126,7 +126,19 @@ __device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2
       // entries include halo copies of B sources this A meets in its own
       // zone: only entries of the A source's own zone count
       const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-      const bool keep = same_zone && (!a.self_only || ia < ib);
+      bool keep = same_zone && (!a.self_only || ia < ib);
+      if (keep && a.hp_order >= 0) {
+        // paper-scheme emulation: count the pair in the smallest shared pixel
+        uint32_t pa[5], pb[5];
+        const double2 ca = a.radecA[ent.x], cb = a.radecB[ent.y];
+        const int na_ = hp_quad(a.hp_order, ca.x, ca.y, a.hp_R, pa);
+        const int nb_ = hp_quad(a.hp_order, cb.x, cb.y, a.hp_R, pb);
+        uint32_t first = 0xffffffffu;
+        for (int u = 0; u < na_; ++u)
+          for (int v = 0; v < nb_; ++v)
+            if (pa[u] == pb[v] && pa[u] < first) first = pa[u];
+        keep = first == a.keysA[ent.x];
+      }
       double tlo = a.t_lo64, thi = a.t_hi64;
       if (a.a_err) pair_chord_thr(pair_radius(a, ia, ib), tlo, thi);
       in = keep && d2 <= tlo;

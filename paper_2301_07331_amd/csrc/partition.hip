@@ -604,11 +604,120 @@ __global__ __launch_bounds__(256) void k_err_max(const double* __restrict__ err,
   if ((threadIdx.x & 63) == 0 && c) atomicMax(out, c);
 }
 
+// ---------------------------------------------------------------------------
+// paper-scheme emulation
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hp_keygen(const double* __restrict__ ra,
+                                                   const double* __restrict__ dec, uint32_t n, int order,
+                                                   double R, uint32_t err_bit, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals,
+                                                   unsigned long long* __restrict__ count, Counters* cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t px[5];
+  int m = 0;
+  if (i < n) {
+    const double a = ra[i], d = dec[i];
+    if (valid_pos(a, d)) m = hp_quad(order, a, d, R, px);
+    else atomicOr(&cnt->err, err_bit);
+  }
+  // wave prefix of the entry counts, one atomic per wave
+  const uint32_t lane = lane_id();
+  uint32_t x = (uint32_t)m;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  const uint32_t total = __shfl(x, 63);
+  unsigned long long base = 0;
+  if (lane == 63 && total) base = atomicAdd(count, (unsigned long long)total);
+  base = __shfl(base, 63);
+  const unsigned long long pos = base + x - (uint32_t)m;
+  for (int k = 0; k < m; ++k) {
+    keys[pos + k] = px[k];
+    vals[pos + k] = i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_radec_gather(const uint32_t* __restrict__ vals, DevCount nc,
+                                                      const double* __restrict__ ra,
+                                                      const double* __restrict__ dec,
+                                                      double2* __restrict__ radec) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc.get()) return;
+  const uint32_t i = vals[p] & IDX_MASK;
+  radec[p] = make_double2(ra[i], dec[i]);
+}
+
+__global__ __launch_bounds__(256) void k_equal_ranges(const uint32_t* __restrict__ keysA, DevCount nac,
+                                                      const uint32_t* __restrict__ lb,
+                                                      const uint32_t* __restrict__ keysB, DevCount nbc,
+                                                      GroupRanges* __restrict__ out) {
+  const uint32_t na = nac.get(), nb = nbc.get();
+  const uint32_t ngroups = (na + GROUP - 1) / GROUP;
+  const uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (grp >= ngroups) return;
+  const uint32_t p0 = grp * GROUP, cnt = min((uint32_t)GROUP, na - p0);
+  RangeList L;
+  L.n = 0;
+  uint32_t q = 0;
+  while (q < cnt) {
+    const uint32_t k = keysA[p0 + q];
+    uint32_t qe = q;
+    while (qe + 1 < cnt && keysA[p0 + qe + 1] == k) ++qe;
+    const uint32_t s = lb[p0 + q];  // first B key >= k
+    const uint32_t e = gallop_upper(keysB, k, s, s, nb);
+    L.add(s, e);
+    q = qe + 1;
+  }
+  while (L.n > MAXR) {
+    int best = 0;
+    uint32_t gap = 0xffffffffu;
+    for (int t = 0; t + 1 < L.n; ++t) {
+      const uint32_t gp = L.s[t + 1] - L.e[t];
+      if (gp < gap) { gap = gp; best = t; }
+    }
+    L.e[best] = L.e[best + 1];
+    for (int t = best + 1; t + 1 < L.n; ++t) {
+      L.s[t] = L.s[t + 1];
+      L.e[t] = L.e[t + 1];
+    }
+    --L.n;
+  }
+  GroupRanges R;
+  for (int t = 0; t < MAXR; ++t) {
+    R.start[t] = t < L.n ? L.s[t] : 0u;
+    R.end[t] = t < L.n ? L.e[t] : 0u;
+  }
+  R.count = (uint32_t)L.n;
+  R.thr32 = 0.0f;
+  R.pad_[0] = R.pad_[1] = 0u;
+  out[grp] = R;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void launch_hp_keygen(const double* ra, const double* dec, uint32_t n, int order, double R, uint32_t err_bit,
+                      uint32_t* keys, uint32_t* vals, unsigned long long* count, Counters* cnt, hipStream_t s) {
+  if (n == 0) return;
+  k_hp_keygen<<<cdiv(n, 256), 256, 0, s>>>(ra, dec, n, order, R, err_bit, keys, vals, count, cnt);
+}
+
+void launch_radec_gather(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
+                         double2* radec, hipStream_t s) {
+  if (n.cap == 0) return;
+  k_radec_gather<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, radec);
+}
+
+void launch_equal_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
+                         const DevCount& nb, GroupRanges* out, hipStream_t s) {
+  const uint32_t ng = cdiv(na.cap, GROUP);
+  if (ng == 0) return;
+  k_equal_ranges<<<cdiv(ng, 256), 256, 0, s>>>(keysA, na, lb, keysB, nb, out);
+}
+
 void launch_err_max(const double* err, uint32_t n, unsigned long long* out_code, Counters* cnt,
                     hipStream_t s) {
   if (n == 0) return;

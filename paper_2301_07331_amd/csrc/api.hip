@@ -268,7 +268,61 @@ struct MatchWs {
   uint32_t* zstart_buf;
   uint2* band;
   uint64_t band_cap;
+  Regions reg;
 };
+
+// Sizes of the two spill-prone work buffers of a call: the band list and
+// the staging slots per output region. Both start from estimates; a call
+// whose counts exceed them runs again with the counted sizes (the counts
+// are deterministic, so the second run fits).
+struct Caps {
+  uint64_t band;
+  uint64_t stage;
+};
+
+uint64_t stage_guess(uint64_t cap) {
+  const uint64_t s = cap / NREG + cap / (4 * NREG) + 4096;
+  return std::min<uint64_t>(s, 1ull << 22);
+}
+
+Caps initial_caps(uint64_t entries, uint64_t cap) { return Caps{(1u << 20) + entries / 64, stage_guess(cap)}; }
+
+void carve_regions(Carve& c, Regions& r, uint64_t S, bool sep) {
+  r.fill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
+  r.cand = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
+  r.S = S;
+  r.pairs = c.take<uint2>((size_t)NREG * S);
+  r.sep = sep ? c.take<double>((size_t)NREG * S) : nullptr;
+}
+
+// True when the call must run again: its band list overflowed, or an output
+// region overflowed although the caller's buffer holds every pair.
+bool regrow(const Counters& h, uint64_t cap, Caps& k) {
+  bool again = false;
+  if (h.n_band > k.band) {
+    k.band = h.n_band + h.n_band / 4 + 1024;
+    again = true;
+  }
+  if (h.n_pairs <= cap && h.region_max > k.stage) {
+    k.stage = h.region_max + 1024;
+    again = true;
+  }
+  return again;
+}
+
+OutArgs out_args(hlc_pair* pairs, double* sep, uint64_t cap, uint2* band, uint64_t band_cap,
+                 const Regions& reg, Counters* cnt) {
+  OutArgs oa{};
+  oa.pairs = reinterpret_cast<uint2*>(pairs);
+  oa.sep = sep;
+  oa.cap = cap;
+  oa.band = band;
+  oa.band_cap = band_cap;
+  oa.cnt = cnt;
+  oa.reg = reg;
+  oa.reg.sep = sep ? reg.sep : nullptr;
+  return oa;
+}
 
 // Everything after the partition: ranges, match, certification.
 void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_arcsec, bool fp32,
@@ -308,22 +362,19 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.b_err = rad.b_err;
   ma.k_sigma = rad.k;
   ma.hp_order = -1;
-  OutArgs oa{};
-  oa.pairs = reinterpret_cast<uint2*>(out_pairs);
-  oa.sep = out_sep;
-  oa.cap = cap;
-  oa.band = w.band;
-  oa.band_cap = w.band_cap;
-  oa.cnt = dev.cnt;
+  const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
+  launch_regions_reset(oa, s);
   if (fp32) launch_match32(ma, oa, s);
   else launch_match64(ma, oa, s);
   if (prof) (void)hipEventRecord(dev.ev[9], s);
   launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, s);
+  launch_compact(oa, s);
   if (prof) (void)hipEventRecord(dev.ev[10], s);
 }
 
-size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, uint64_t band_cap,
+size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, const Caps& caps,
                       bool need_zstart) {
+  const uint64_t band_cap = caps.band;
   const uint32_t nA = std::max(na_entries, 1u);
   w.lb = c.take<uint32_t>(nA);
   w.ranges = c.take<GroupRanges>((nA + GROUP - 1) / GROUP);
@@ -332,6 +383,7 @@ size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, 
   w.zstartB = nullptr;
   w.band = c.take<uint2>(band_cap);
   w.band_cap = band_cap;
+  carve_regions(c, w.reg, caps.stage, true);
   return c.off;
 }
 
@@ -404,9 +456,8 @@ int read_counters(Device& dev, hipStream_t s, bool prof) {
 
 int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
                 const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
-                double* out_sep, const hlc_opts* o, uint64_t band_cap, uint64_t* band_needed,
-                const Radii& rad) {
-  *band_needed = 0;
+                double* out_sep, const hlc_opts* o, Caps& caps, bool* again, const Radii& rad) {
+  *again = false;
   Device* dev = nullptr;
   HLC_CHECK(get_device(&dev));
   hipStream_t s = (hipStream_t)o->stream;
@@ -427,7 +478,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     carve_side(c, B, 2 * nB, !fp32, fp32);
     carve_sort(c, sc, std::max(nA, 2 * nB));
     carve_tables(c, tb, g, fp32);
-    carve_match_ws(c, w, nA, g, band_cap, true);
+    carve_match_ws(c, w, nA, g, caps, true);
   };
   Carve sizing{nullptr};
   lay(sizing);
@@ -459,8 +510,8 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     *o->n_pairs = 0;
     return HLC_E_INVAL;
   }
-  if (h.n_band > band_cap) {
-    *band_needed = h.n_band;
+  if (regrow(h, (uint64_t)o->capacity, caps)) {
+    *again = true;
     return HLC_OK;
   }
   fill_stats(h, na, nb, nb + (int64_t)h.n_halo, g);
@@ -469,17 +520,15 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   return h.n_pairs > (unsigned long long)o->capacity ? HLC_E_OVERFLOW : HLC_OK;
 }
 
-// xmatch_impl with the band-list retry.
+// xmatch_impl with the work-buffer retry.
 int xmatch_core(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
                 const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
                 double* out_sep, const hlc_opts* o, const Radii& rad = Radii{nullptr, nullptr, 0.0}) {
-  uint64_t band_cap = (1u << 20) + (uint64_t)(na + nb) / 64;
+  Caps caps = initial_caps((uint64_t)(na + nb), (uint64_t)o->capacity);
   for (int attempt = 0; attempt < 3; ++attempt) {
-    uint64_t need = 0;
-    int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, band_cap,
-                         &need, rad);
-    if (need == 0) return st;
-    band_cap = need + need / 4 + 1024;
+    bool again = false;
+    int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, caps, &again, rad);
+    if (!again) return st;
   }
   return HLC_E_NOMEM;
 }
@@ -605,7 +654,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
     HLC_CHECK(get_device(&dev));
     hipStream_t s = (hipStream_t)opts->stream;
     const uint32_t capA = 5u * (uint32_t)na, capB = 5u * (uint32_t)nb;
-    uint64_t band_cap = (1u << 20) + (uint64_t)(capA + capB) / 64;
+    Caps caps = initial_caps((uint64_t)capA + capB, (uint64_t)opts->capacity);
     for (int attempt = 0; attempt < 3; ++attempt) {
       Side A, B;
       SortScratch sc;
@@ -618,7 +667,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
         carve_side(c, A, capA, true, true);
         carve_side(c, B, capB, true, true);
         carve_sort(c, sc, std::max(capA, capB));
-        carve_match_ws(c, w, capA, g, band_cap, false);
+        carve_match_ws(c, w, capA, g, caps, false);
       };
       Carve sz{nullptr};
       lay(sz);
@@ -658,22 +707,16 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       ma.H_hi = th.H_hi;
       ma.hp_order = order;
       ma.hp_R = R;
-      OutArgs oa{};
-      oa.pairs = reinterpret_cast<uint2*>(out_pairs);
-      oa.sep = (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec;
-      oa.cap = (uint64_t)opts->capacity;
-      oa.band = w.band;
-      oa.band_cap = band_cap;
-      oa.cnt = dev->cnt;
+      const OutArgs oa = out_args(out_pairs, (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec,
+                                  (uint64_t)opts->capacity, w.band, w.band_cap, w.reg, dev->cnt);
+      launch_regions_reset(oa, s);
       launch_match64(ma, oa, s);
       launch_certify(a_ra, a_dec, b_ra, b_dec, r_arcsec, th.H_lo, th.H_hi, Radii{nullptr, nullptr, 0.0}, oa, s);
+      launch_compact(oa, s);
       HLC_CHECK(read_counters(*dev, s, false));
       const Counters& h = *dev->cnt_host;
       if (h.err) return HLC_E_INVAL;
-      if (h.n_band > band_cap) {
-        band_cap = h.n_band + h.n_band / 4 + 1024;
-        continue;
-      }
+      if (regrow(h, (uint64_t)opts->capacity, caps)) continue;
       std::memset(&g_stats, 0, sizeof(g_stats));
       g_stats.na = na;
       g_stats.nb = nb;
@@ -806,14 +849,14 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       std::memset(&g_stats, 0, sizeof(g_stats));
       return HLC_OK;
     }
-    uint64_t band_cap = (1u << 20) + (uint64_t)(A->side.cnt.cap + B->side.cnt.cap) / 64;
+    Caps caps = initial_caps((uint64_t)A->side.cnt.cap + B->side.cnt.cap, (uint64_t)opts->capacity);
     for (int attempt = 0; attempt < 3; ++attempt) {
       MatchWs w;
       Carve sizing{nullptr};
-      carve_match_ws(sizing, w, A->side.cnt.cap, g, band_cap, false);
+      carve_match_ws(sizing, w, A->side.cnt.cap, g, caps, false);
       HLC_CHECK(ensure_ws(*dev, sizing.off + 256));
       Carve c{(char*)dev->ws};
-      carve_match_ws(c, w, A->side.cnt.cap, g, band_cap, false);
+      carve_match_ws(c, w, A->side.cnt.cap, g, caps, false);
       w.zstartB = B->zstart;
       if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
       launch_zero_counters(dev->cnt, s);
@@ -822,10 +865,7 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
             (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec, (uint64_t)opts->capacity, prof, s);
       HLC_CHECK(read_counters(*dev, s, prof));
       const Counters& h = *dev->cnt_host;
-      if (h.n_band > band_cap) {
-        band_cap = h.n_band + h.n_band / 4 + 1024;
-        continue;
-      }
+      if (regrow(h, (uint64_t)opts->capacity, caps)) continue;
       fill_stats(h, A->side.n_src, B->side.n_src, B->side.cnt.cap, g);
       if (prof) fill_times(*dev, false);
       *opts->n_pairs = (int64_t)h.n_pairs;
@@ -982,11 +1022,14 @@ struct BatchBufs {
   double2 *radecA, *radecB;
   uint2* band;
   uint32_t* band_job;
+  uint64_t band_cap;
+  Regions reg;
   unsigned long long* jcount;
   SortScratch sc;
 };
 
-void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, uint64_t band_cap, bool own_jcount) {
+void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Caps& caps, bool own_jcount) {
+  const uint64_t band_cap = caps.band;
   const uint32_t NA = std::max<uint32_t>((uint32_t)P.NA, 1), NB2 = std::max<uint32_t>(2 * (uint32_t)P.NB, 1);
   const uint32_t ng = (NA + GROUP - 1) / GROUP;
   b.bounds = c.take<unsigned long long>(4 * (size_t)std::max(P.njobs, 1));
@@ -1016,6 +1059,8 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, uint64_t
   b.zstart = c.take<uint32_t>(std::max<uint32_t>(P.ztotal, 1));
   b.band = c.take<uint2>(band_cap);
   b.band_job = c.take<uint32_t>(band_cap);
+  b.band_cap = band_cap;
+  carve_regions(c, b.reg, caps.stage, true);
   b.jcount = own_jcount ? c.take<unsigned long long>(std::max(P.njobs, 1)) : nullptr;
 }
 
@@ -1024,7 +1069,7 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, uint64_t
 void batch_enqueue(Device& dev, BatchState& BS, const BatchPlan& P, const BatchBufs& b, const double* a_ra,
                    const double* a_dec, const double* b_ra, const double* b_dec, hlc_pair* out_pairs,
                    double* out_sep, uint64_t cap, unsigned long long* jcount, double factor, bool fp32,
-                   uint64_t band_cap, hipStream_t s) {
+                   hipStream_t s) {
   const uint32_t NA = (uint32_t)P.NA, NB = (uint32_t)P.NB;
   launch_zero_counters(dev.cnt, s);
   launch_zero_u64(jcount, (uint32_t)P.njobs, s);
@@ -1070,18 +1115,14 @@ void batch_enqueue(Device& dev, BatchState& BS, const BatchPlan& P, const BatchB
   ma.geo = b.geo;
   ma.lb_bits = P.lb_bits;
   ma.job_count = jcount;
-  OutArgs oa{};
-  oa.pairs = reinterpret_cast<uint2*>(out_pairs);
-  oa.sep = out_sep;
-  oa.cap = cap;
-  oa.band = b.band;
+  OutArgs oa = out_args(out_pairs, out_sep, cap, b.band, b.band_cap, b.reg, dev.cnt);
   oa.band_job = b.band_job;
-  oa.band_cap = band_cap;
-  oa.cnt = dev.cnt;
+  launch_regions_reset(oa, s);
   // persistent grid: four 256-thread blocks per CU (the LDS queue allows four)
   const uint32_t nblocks = std::max<uint32_t>(1, std::min<uint32_t>(4u * (uint32_t)BS.ncu, (ng + 15) / 16));
   launch_batch_match(ma, oa, fp32, nblocks, s);
   launch_batch_certify(a_ra, a_dec, b_ra, b_dec, BS.d_jobs, oa, jcount, s);
+  launch_compact(oa, s);
 }
 
 int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const double* a_dec,
@@ -1156,9 +1197,9 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
     BS.tables_hash = th;
   }
 
-  uint64_t band_cap = (1u << 20) + (P.NA + P.NB) / 64;
   unsigned long long* jcount = reinterpret_cast<unsigned long long*>(job_pair_count);
   const uint64_t cap = (uint64_t)o->capacity;
+  Caps caps = initial_caps((uint64_t)(P.NA + P.NB), cap);
   double* sep = (o->flags & HLC_NO_SEP) ? nullptr : out_sep;
 
   // zone-height factor: given, cached, or tuned now (eager timed runs)
@@ -1174,10 +1215,10 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
   for (int attempt = 0; attempt < 3; ++attempt) {
     BatchBufs b;
     Carve sz{nullptr};
-    carve_batch(sz, b, P, fp32, band_cap, jcount == nullptr);
+    carve_batch(sz, b, P, fp32, caps, jcount == nullptr);
     HLC_CHECK(ensure_ws(*dev, sz.off + 256));
     Carve c{(char*)dev->ws};
-    carve_batch(c, b, P, fp32, band_cap, jcount == nullptr);
+    carve_batch(c, b, P, fp32, caps, jcount == nullptr);
     unsigned long long* jc = jcount ? jcount : b.jcount;
     if (!(factor > 0)) {
       // autotune: time each candidate on this batch
@@ -1185,7 +1226,7 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
       double best_t = 1e30, best_f = 1.0;
       for (double f : {0.35, 0.7, 1.4, 2.8}) {
         HLC_TRY(hipEventRecord(BS.ev_t0, s));
-        batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, f, fp32, band_cap, s);
+        batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, f, fp32, s);
         HLC_TRY(hipEventRecord(BS.ev_t1, s));
         HLC_TRY(hipStreamSynchronize(s));
         float ms = 0.f;
@@ -1200,12 +1241,13 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
     uint64_t gk = fnv(&th, sizeof th);
     const void* keyp[] = {a_ra, a_dec, b_ra, b_dec, out_pairs, sep, jc, dev->ws, dev->cnt};
     gk = fnv(keyp, sizeof keyp, gk);
-    const double keyd[] = {factor, (double)cap, (double)band_cap, (double)fp32, (double)dev->ws_bytes};
+    const double keyd[] = {factor, (double)cap, (double)caps.band, (double)caps.stage, (double)fp32,
+                           (double)dev->ws_bytes};
     gk = fnv(keyd, sizeof keyd, gk);
     if (BS.exec == nullptr || BS.graph_key != gk) {
       drop_graph(BS);
       HLC_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, factor, fp32, band_cap, s);
+      batch_enqueue(*dev, BS, P, b, a_ra, a_dec, b_ra, b_dec, out_pairs, sep, cap, jc, factor, fp32, s);
       hipError_t e = hipStreamEndCapture(s, &BS.graph);
       if (e != hipSuccess) {
         BS.graph = nullptr;
@@ -1230,8 +1272,7 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
       *o->n_pairs = 0;
       return HLC_E_INVAL;
     }
-    if (h.n_band > band_cap) {
-      band_cap = h.n_band + h.n_band / 4 + 1024;
+    if (regrow(h, cap, caps)) {
       drop_graph(BS);
       continue;
     }

@@ -475,19 +475,17 @@ constexpr int QCAP = 64 * (GROUP + 1);
 
 __device__ inline void bemit(bool in, uint32_t ia, uint32_t ib, double sep, int32_t job,
                              const OutArgs& o, unsigned long long* job_count) {
-  uint64_t m = __ballot(in);
-  if (m == 0) return;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(&o.cnt->n_pairs, (unsigned long long)__popcll(m));
-  base = __shfl(base, (int)leader);
-  if (in) {
-    unsigned long long slot = base + rank_in(m);
-    if (slot < o.cap) {
-      o.pairs[slot] = make_uint2(ia, ib);
-      if (o.sep) o.sep[slot] = sep;
-    }
-    if (job_count) atomicAdd(&job_count[job], 1ull);
+  emit_wave(in, ia, ib, sep, o);
+  if (!job_count) return;
+  // one atomic per distinct job among the wave's pairs (the four groups of
+  // a wave seldom span more than two jobs)
+  uint64_t rem = __ballot(in);
+  while (rem) {
+    const uint32_t leader = (uint32_t)__builtin_ctzll(rem);
+    const int32_t j0 = __shfl(job, (int)leader);
+    const uint64_t same = __ballot(in && job == j0);
+    if (lane_id() == leader) atomicAdd(&job_count[j0], (unsigned long long)__popcll(same));
+    rem &= ~same;
   }
 }
 
@@ -510,7 +508,7 @@ __device__ inline void bband(bool band, uint32_t ia, uint32_t ib, int32_t job, c
 template <bool FP32>
 __device__ void bflush(const BatchMatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn) {
   const uint32_t lane = lane_id();
-  if (lane == 0) atomicAdd(&o.cnt->n_cand, (unsigned long long)qn);
+  count_candidates(qn, o);
   for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
     const uint32_t e = b0 + lane;
     bool in = false, band = false;
@@ -580,13 +578,12 @@ __global__ __launch_bounds__(MT) void k_batch_match(BatchMatchArgs a, OutArgs o)
   uint32_t qn = 0;
   const uint32_t na = a.na.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
-  // persistent: each wave takes four groups at a time from the LPT order;
-  // every wave leaves once the queue is drained
-  while (true) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(a.queue, 4u);
-    item = __shfl(item, 0);
-    if (item >= ngroups) break;
+  // persistent: wave w of W takes the four groups at LPT positions
+  // 4 (w + i W), i = 0, 1, ... (largest first, dealt round-robin; no queue
+  // atomics); every wave leaves after its last item
+  const uint32_t W = gridDim.x * WAVES;
+  const uint32_t wid = blockIdx.x * WAVES + w;
+  for (uint32_t item = 4u * wid; item < ngroups; item += 4u * W) {
     const uint32_t slot = item + row;
     const bool grp_ok = slot < ngroups;
     const uint32_t grp = grp_ok ? a.order[slot] : 0u;
@@ -684,11 +681,7 @@ __global__ __launch_bounds__(256) void k_batch_certify(const double* __restrict_
       }
     }
     if (in) {
-      const unsigned long long slot = atomicAdd(&o.cnt->n_pairs, 1ull);
-      if (slot < o.cap) {
-        o.pairs[slot] = make_uint2(e.x, e.y);
-        if (o.sep) o.sep[slot] = sep;
-      }
+      emit_one(e.x, e.y, sep, o);
       if (job_count) atomicAdd(&job_count[j], 1ull);
     }
   }

@@ -71,6 +71,8 @@ struct Counters {
   unsigned int err;               // bit 0: bad coordinate in A, bit 1: in B
   unsigned int queue;             // work-queue head of persistent kernels
   unsigned long long aux[2];      // entry counts of multi-entry keygens (A, B)
+  unsigned long long region_max;  // largest output-region fill (compaction)
+  unsigned long long pad_;
 };
 
 struct Rec64 {      // FP64 working record (32 B)

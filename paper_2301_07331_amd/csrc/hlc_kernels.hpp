@@ -45,6 +45,22 @@ void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb
                    GroupRanges* out, hipStream_t s);
 
 // ---- match.hip -------------------------------------------------------------
+// Output allocation. A single counter bumped by every wave serialises at the
+// memory side (device-scope atomics on one address), so pairs are appended
+// to NREG striped staging regions instead (region = wave index mod NREG,
+// counters 256 B apart) and a compaction kernel packs the regions into the
+// caller's buffer in region order.
+constexpr int NREG = 256;
+constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
+
+struct Regions {
+  unsigned long long* fill;     // NREG * REG_STRIDE; fill[k * REG_STRIDE] = pairs sent to region k
+  unsigned long long* cand;     // NREG * REG_STRIDE; certified candidates (statistics)
+  uint2* pairs;                 // NREG * S staging
+  double* sep;                  // NREG * S staging, or nullptr
+  unsigned long long S;         // staging slots per region
+};
+
 struct OutArgs {
   uint2* pairs;                 // caller buffer (a, b)
   double* sep;                  // caller buffer or nullptr
@@ -53,7 +69,47 @@ struct OutArgs {
   uint32_t* band_job;           // batched form: job of each band entry (else nullptr)
   unsigned long long band_cap;
   Counters* cnt;
+  Regions reg;
 };
+
+__device__ inline uint32_t wave_region() {
+  return ((blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6)) & (NREG - 1);
+}
+
+// Pairs of the lanes with `in` set, appended to this wave's region with one
+// atomic.
+__device__ inline void emit_wave(bool in, uint32_t ia, uint32_t ib, double sep, const OutArgs& o) {
+  const uint64_t m = __ballot(in);
+  if (m == 0) return;
+  const uint32_t k = wave_region();
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(&o.reg.fill[k * REG_STRIDE], (unsigned long long)__popcll(m));
+  base = __shfl(base, (int)leader);
+  if (in) {
+    const unsigned long long slot = base + rank_in(m);
+    if (slot < o.reg.S) {
+      const unsigned long long at = (unsigned long long)k * o.reg.S + slot;
+      o.reg.pairs[at] = make_uint2(ia, ib);
+      if (o.reg.sep) o.reg.sep[at] = sep;
+    }
+  }
+}
+
+// One pair from one thread (rare paths: band certification).
+__device__ inline void emit_one(uint32_t ia, uint32_t ib, double sep, const OutArgs& o) {
+  const uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) & (NREG - 1);
+  const unsigned long long slot = atomicAdd(&o.reg.fill[k * REG_STRIDE], 1ull);
+  if (slot < o.reg.S) {
+    const unsigned long long at = (unsigned long long)k * o.reg.S + slot;
+    o.reg.pairs[at] = make_uint2(ia, ib);
+    if (o.reg.sep) o.reg.sep[at] = sep;
+  }
+}
+
+__device__ inline void count_candidates(uint32_t qn, const OutArgs& o) {
+  if (lane_id() == 0) atomicAdd(&o.reg.cand[wave_region() * REG_STRIDE], (unsigned long long)qn);
+}
 
 struct MatchArgs {
   const GroupRanges* ranges;
@@ -95,6 +151,10 @@ struct Radii {
   double k;
 };
 
+// zero the region counters / pack the regions into the caller's buffer
+// (n_pairs, n_cand and region_max of *o.cnt are set by the packing)
+void launch_regions_reset(const OutArgs& o, hipStream_t s);
+void launch_compact(const OutArgs& o, hipStream_t s);
 void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s);
 void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s);
 // Re-decide the band list from the original coordinates: FP64 haversine,

@@ -74,22 +74,6 @@ __device__ inline void pair_hav_thr(double r_as, double& Hlo, double& Hhi) {
   Hhi = H * (1.0 + EPS_BAND);
 }
 
-__device__ inline void emit_pairs(bool in, uint32_t ia, uint32_t ib, double sep, const OutArgs& o) {
-  uint64_t m = __ballot(in);
-  if (m == 0) return;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(&o.cnt->n_pairs, (unsigned long long)__popcll(m));
-  base = __shfl(base, (int)leader);
-  if (in) {
-    unsigned long long slot = base + rank_in(m);
-    if (slot < o.cap) {
-      o.pairs[slot] = make_uint2(ia, ib);
-      if (o.sep) o.sep[slot] = sep;
-    }
-  }
-}
-
 __device__ inline void emit_band(bool band, uint32_t ia, uint32_t ib, const OutArgs& o) {
   uint64_t m = __ballot(band);
   if (m == 0) return;
@@ -108,7 +92,7 @@ __device__ inline void emit_band(bool band, uint32_t ia, uint32_t ib, const OutA
 // ---------------------------------------------------------------------------
 __device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn) {
   const uint32_t lane = lane_id();
-  if (lane == 0) atomicAdd(&o.cnt->n_cand, (unsigned long long)qn);
+  count_candidates(qn, o);
   for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
     const uint32_t e = b0 + lane;
     bool in = false, band = false;
@@ -145,7 +129,7 @@ __device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2
       band = keep && !in && d2 <= thi;
       if (in) sep = 2.0 * asin(0.5 * sqrt(d2)) * RAD2ARCSEC;
     }
-    emit_pairs(in, ia, ib, sep, o);
+    emit_wave(in, ia, ib, sep, o);
     emit_band(band, ia, ib, o);
   }
 }
@@ -254,7 +238,7 @@ __device__ inline void cell_centre(const MatchArgs& a, uint32_t k, double& cx, d
 
 __device__ inline void flush32(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn) {
   const uint32_t lane = lane_id();
-  if (lane == 0) atomicAdd(&o.cnt->n_cand, (unsigned long long)qn);
+  count_candidates(qn, o);
   for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
     const uint32_t e = b0 + lane;
     bool in = false, band = false;
@@ -275,7 +259,7 @@ __device__ inline void flush32(const MatchArgs& a, const OutArgs& o, const uint2
       band = keep && !in && h <= Hhi;
       if (in) sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
     }
-    emit_pairs(in, ia, ib, sep, o);
+    emit_wave(in, ia, ib, sep, o);
     emit_band(band, ia, ib, o);
   }
 }
@@ -384,17 +368,68 @@ __global__ __launch_bounds__(256) void k_certify(const double* __restrict__ a_ra
         sep = 2.0 * asin(sqrt(hd.hi)) * RAD2ARCSEC;
       }
     }
-    if (in) {
-      unsigned long long slot = atomicAdd(&o.cnt->n_pairs, 1ull);
-      if (slot < o.cap) {
-        o.pairs[slot] = make_uint2(e.x, e.y);
-        if (o.sep) o.sep[slot] = sep;
+    if (in) emit_one(e.x, e.y, sep, o);
+  }
+}
+
+__global__ void k_regions_reset(Regions reg) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NREG) {
+    reg.fill[i * REG_STRIDE] = 0ull;
+    reg.cand[i * REG_STRIDE] = 0ull;
+  }
+}
+
+// Block k packs region k after the regions before it; block 0 also writes
+// the totals. Contents beyond the caller's capacity are dropped (the call
+// then reports the required count).
+__global__ __launch_bounds__(256) void k_compact(OutArgs o) {
+  __shared__ unsigned long long s_off;
+  const uint32_t k = blockIdx.x;
+  if (threadIdx.x < 64) {
+    unsigned long long off = 0, tot = 0, cand = 0, mx = 0;
+    for (uint32_t i = threadIdx.x; i < NREG; i += 64) {
+      const unsigned long long f = o.reg.fill[i * REG_STRIDE];
+      const unsigned long long used = f < o.reg.S ? f : o.reg.S;
+      if (i < k) off += used;
+      tot += f;
+      cand += o.reg.cand[i * REG_STRIDE];
+      mx = f > mx ? f : mx;
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+      off += __shfl_xor(off, d);
+      tot += __shfl_xor(tot, d);
+      cand += __shfl_xor(cand, d);
+      const unsigned long long om = __shfl_xor(mx, d);
+      mx = om > mx ? om : mx;
+    }
+    if (threadIdx.x == 0) {
+      s_off = off;
+      if (k == 0) {
+        o.cnt->n_pairs = tot;
+        o.cnt->n_cand = cand;
+        o.cnt->region_max = mx;
       }
     }
+  }
+  __syncthreads();
+  const unsigned long long f = o.reg.fill[k * REG_STRIDE];
+  const unsigned long long n = f < o.reg.S ? f : o.reg.S;
+  const unsigned long long off = s_off;
+  for (unsigned long long j = threadIdx.x; j < n; j += blockDim.x) {
+    const unsigned long long dst = off + j;
+    if (dst >= o.cap) break;
+    const unsigned long long src = (unsigned long long)k * o.reg.S + j;
+    o.pairs[dst] = o.reg.pairs[src];
+    if (o.sep) o.sep[dst] = o.reg.sep[src];
   }
 }
 
 }  // namespace
+
+void launch_regions_reset(const OutArgs& o, hipStream_t s) { k_regions_reset<<<1, NREG, 0, s>>>(o.reg); }
+
+void launch_compact(const OutArgs& o, hipStream_t s) { k_compact<<<NREG, 256, 0, s>>>(o); }
 
 void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
   uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;

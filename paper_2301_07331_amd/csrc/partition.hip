@@ -44,46 +44,90 @@ __global__ void k_zero_counters(Counters* c) {
 // ---------------------------------------------------------------------------
 // keygen
 // ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_w) {
+  const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t s = s_w[k];
+    if ((uint32_t)k < w) wbase += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+// Each block keys KG_ITEMS * 256 sources; the Dec-halo copies of the block
+// are placed with a single atomic on the halo counter (one per block keeps
+// the contended counter off the critical path).
+constexpr int KG_ITEMS = 16;
+constexpr uint32_t KG_TILE = KG_ITEMS * 256;
+
 __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
                                                 uint32_t* __restrict__ keys,
                                                 uint32_t* __restrict__ vals, Counters* cnt) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool in = i < n;
-  double a = 0.0, d = 0.0;
-  if (in) {
-    a = ra[i];
-    d = dec[i];
+  __shared__ uint32_t s_w[4];
+  __shared__ unsigned long long s_base;
+  const uint32_t t = threadIdx.x;
+  const uint32_t base = blockIdx.x * KG_TILE;
+  uint32_t hkey[KG_ITEMS];
+  uint32_t need = 0;  // bit j: item j has a halo copy
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < KG_ITEMS; ++j) {
+    const uint32_t i = base + (uint32_t)j * 256u + t;
+    hkey[j] = 0u;
+    if (i < n) {
+      double a = ra[i], d = dec[i];
+      const bool ok = valid_pos(a, d);
+      if (!ok) {
+        bad = true;
+        a = 0.0;
+        d = 0.0;
+      }
+      const int32_t z = zone_of(g, d);
+      const uint32_t b = bin_of(g, a);
+      keys[i] = make_key(g, z, b);
+      vals[i] = i;
+      if (halo && ok) {
+        // the zone height is >= 2 r, so the padded Dec window reaches at
+        // most one neighbouring zone
+        const int32_t zl = zone_of(g, d - g.rpad_deg), zh = zone_of(g, d + g.rpad_deg);
+        const int32_t other = (zl != z) ? zl : zh;
+        if (other != z) {
+          hkey[j] = make_key(g, other, b);
+          need |= 1u << j;
+        }
+      }
+    }
   }
-  bool ok = !in || valid_pos(a, d);
-  if (!ok) {
-    atomicOr(&cnt->err, err_bit);
-    a = 0.0;
-    d = 0.0;
-  }
-  int32_t z = zone_of(g, d);
-  uint32_t b = bin_of(g, a);
-  if (in) {
-    keys[i] = make_key(g, z, b);
-    vals[i] = i;
-  }
+  if (bad) atomicOr(&cnt->err, err_bit);
   if (!halo) return;
-  // Dec halo: also key the source into the neighbouring zone when its
-  // padded Dec window reaches it (the zone height is >= 2 r, so at most one).
-  int32_t zl = zone_of(g, d - g.rpad_deg), zh = zone_of(g, d + g.rpad_deg);
-  int32_t other = (zl != z) ? zl : zh;
-  bool need = in && ok && other != z;
-  uint64_t m = __ballot(need);
-  if (m == 0) return;
-  uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(&cnt->n_halo, (unsigned long long)__popcll(m));
-  base = __shfl(base, (int)leader);
-  if (need) {
-    uint64_t pos = (uint64_t)n + base + rank_in(m);
-    keys[pos] = make_key(g, other, b);
-    vals[pos] = i | HALO_BIT;
+  uint32_t total;
+  const uint32_t off = block_exclusive_scan((uint32_t)__popc(need), &total, s_w);
+  if (total == 0) return;
+  if (t == 0) s_base = atomicAdd(&cnt->n_halo, (unsigned long long)total);
+  __syncthreads();
+  uint64_t pos = (uint64_t)n + s_base + off;
+#pragma unroll
+  for (int j = 0; j < KG_ITEMS; ++j) {
+    if (need & (1u << j)) {
+      keys[pos] = hkey[j];
+      vals[pos] = (base + (uint32_t)j * 256u + t) | HALO_BIT;
+      ++pos;
+    }
   }
 }
 
@@ -107,29 +151,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
   }
   __syncthreads();
   counts[t * ntiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
-}
-
-// Block-wide exclusive scan of one value per thread (256 threads).
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_w) {
-  const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t y = __shfl_up(x, off);
-    if (lane >= (uint32_t)off) x += y;
-  }
-  if (lane == 63) s_w[w] = x;
-  __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    uint32_t s = s_w[k];
-    if ((uint32_t)k < w) wbase += s;
-    tot += s;
-  }
-  __syncthreads();
-  *total = tot;
-  return wbase + x - v;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
@@ -735,7 +756,7 @@ void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64,
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s) {
   if (n == 0) return;
-  k_keygen<<<cdiv(n, 256), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt);
+  k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt);
 }
 
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }

@@ -1,11 +1,14 @@
 """Benchmark: A-sources matched per second on the 10M x 10M full-sky cross-match.
 
 One step = one hlc_xmatch call (keygen, both radix sorts, layouts, B ranges,
-match, certification, count read-back) on FP64 inputs already resident in
-HBM. The headline value uses the FP32+recheck filter; the plain FP64 filter
-is timed beside it. Prints one JSON line.
+filter, certification, output packing, count read-back) on FP64 inputs
+already resident in HBM. The headline value uses the FP32+recheck filter;
+the plain FP64 filter is timed beside it. Also measured (the "forms" field):
+the batched form on 10,000 cone jobs against one plain FP64 call per job,
+and the emulated HEALPix + quad-direction partition (completeness loss
+against the exact pair set, and time). Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms xmatch,batch,quad]
 """
 from __future__ import annotations
 
@@ -21,14 +24,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per launch of the match kernels: the working layout of
-# both sides read once, the pair output written once (a, b u32 + sep f64).
+# Algorithmic bytes per launch of the filter kernel (the dominant kernel):
+# the working records of both sides read once, each candidate (A position,
+# B position: 2 x u32) written once.
 #   FP64 form: 32 B per A record, 32 B per B entry (x, y, z f64 + index).
-#   FP32 form: 16 B per A record + 4 B key, 16 B + 4 B key per B entry, plus
-#              the FP64 (ra, dec) of both sides of each candidate (32 B).
+#   FP32 form: 16 B per A record, 16 B per B entry (x, y, z f32 + index).
 MATCH_BYTES = {
-    "fp64": lambda na, nbh, npairs, ncand: 32 * na + 32 * nbh + 16 * npairs,
-    "fp32": lambda na, nbh, npairs, ncand: 20 * na + 20 * nbh + 32 * ncand + 16 * npairs,
+    "fp64": lambda na, nbh, npairs, ncand: 32 * na + 32 * nbh + 8 * ncand,
+    "fp32": lambda na, nbh, npairs, ncand: 16 * na + 16 * nbh + 8 * ncand,
 }
 # Whole-call canonical bytes: FP64 (ra, dec) of every source read once and
 # every pair written once.
@@ -47,7 +50,88 @@ def parse():
     p.add_argument("--zone-height", type=float, default=0.0, help="arcsec; 0 = automatic")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    p.add_argument("--forms", default="xmatch,batch,quad",
+                   help="xmatch (the headline, always run), batch (10,000 jobs), quad (paper-scheme emulation)")
     return p.parse_args()
+
+
+def bench_batch(hlc, torch, dev, steps, warmup):
+    """The batched form on 10,000 cone jobs, FP32 and FP64, against one plain
+    FP64 hlc_xmatch call per job (the same jobs, the same pair set)."""
+    import numpy as np
+    import synth
+    t0 = time.time()
+    b = synth.batch_jobs()
+    jobs = [(int(b.a_off[j]), int(b.na[j]), int(b.b_off[j]), int(b.nb[j]), float(b.r_arcsec[j]))
+            for j in range(b.njobs)]
+    print(f"[bench] generated {b.njobs} jobs ({len(b.a_ra)} + {len(b.b_ra)} sources) in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    a_ra, a_dec, b_ra, b_dec = (torch.from_numpy(x).to(dev) for x in (b.a_ra, b.a_dec, b.b_ra, b.b_dec))
+    cap = len(b.a_ra) // 2 + 1024
+    out = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    sep = torch.empty(cap, dtype=torch.float64, device=dev)
+    cnt = torch.empty(len(jobs), dtype=torch.int64, device=dev)
+    res = {}
+    for name, prec in (("fp32", hlc.HLC_FP32_RECHECK), ("fp64", hlc.HLC_FP64)):
+        for _ in range(max(1, warmup)):  # the first call tunes the zone-height factor
+            st, n = hlc.hlc_xmatch_batch(jobs, a_ra, a_dec, b_ra, b_dec, out, sep, cnt, precision=prec)
+            if st != hlc.HLC_OK:
+                raise hlc.HLCError(st, "batch warmup")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, n = hlc.hlc_xmatch_batch(jobs, a_ra, a_dec, b_ra, b_dec, out, sep, cnt, precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        res[name] = {"ms_per_call": ms, "a_sources_per_s": len(b.a_ra) / (ms * 1e-3), "pairs": int(n)}
+        print(f"[bench] batch {name}: {ms:.3f} ms/call, {n} pairs", file=sys.stderr, flush=True)
+    # plain FP64: one call per job
+    jout = torch.empty((max(int(b.na.max()), 1024), 2), dtype=torch.int32, device=dev)
+    jsep = torch.empty(jout.shape[0], dtype=torch.float64, device=dev)
+    total = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (ao, na, bo, nb, r) in jobs:
+        if na == 0 or nb == 0:
+            continue
+        st, n = hlc.hlc_xmatch(a_ra[ao:ao + na], a_dec[ao:ao + na], b_ra[bo:bo + nb], b_dec[bo:bo + nb], r,
+                               jout, jsep, precision=hlc.HLC_FP64)
+        if st == hlc.HLC_E_OVERFLOW:
+            jout = torch.empty((n + 1024, 2), dtype=torch.int32, device=dev)
+            jsep = torch.empty(n + 1024, dtype=torch.float64, device=dev)
+            st, n = hlc.hlc_xmatch(a_ra[ao:ao + na], a_dec[ao:ao + na], b_ra[bo:bo + nb], b_dec[bo:bo + nb], r,
+                                   jout, jsep, precision=hlc.HLC_FP64)
+        if st != hlc.HLC_OK:
+            raise hlc.HLCError(st, "per-job call")
+        total += n
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    res["per_job_fp64"] = {"ms_per_call": ms, "a_sources_per_s": len(b.a_ra) / (ms * 1e-3), "pairs": int(total)}
+    print(f"[bench] per-job FP64 loop: {ms:.1f} ms, {total} pairs", file=sys.stderr, flush=True)
+    if not (res["fp32"]["pairs"] == res["fp64"]["pairs"] == total):
+        raise RuntimeError(f"batched and per-job pair counts differ: {res}")
+    res["workload"] = f"{b.njobs} cone jobs, {len(b.a_ra)} A + {len(b.b_ra)} B sources, r 0.5-3 arcsec"
+    return res
+
+
+def bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, exact_pairs):
+    """The paper's HEALPix + quad-direction partition, emulated on the same
+    workload: pairs it finds (a subset of the exact set), the loss, and time."""
+    res = {}
+    for order in (10, 12, 13):
+        hlc.hlc_xmatch_quad(a_ra, a_dec, b_ra, b_dec, r, order, out, sep)  # warm the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, n = hlc.hlc_xmatch_quad(a_ra, a_dec, b_ra, b_dec, r, order, out, sep)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if st != hlc.HLC_OK:
+            raise hlc.HLCError(st, f"quad order {order}")
+        res[f"order{order}"] = {"ms": ms, "pairs": int(n), "lost": int(exact_pairs - n),
+                                "loss_frac": (exact_pairs - n) / exact_pairs}
+        print(f"[bench] quad order {order}: {ms:.2f} ms, {n} pairs ({exact_pairs - n} lost)", file=sys.stderr,
+              flush=True)
+    return res
 
 
 def main():
@@ -124,11 +208,12 @@ def main():
     head = results.get("fp32") or next(iter(results.values()))
     head_name = "fp32" if "fp32" in results else next(iter(results))
     value = na / (head["ms_per_step"] * 1e-3)
-    # dominant kernel of the headline form: the match kernel (one launch per step)
+    # dominant kernel of the headline form: the filter kernel (one launch per
+    # step, timed by HIP events on the call's stream)
     t_match = head["stage_ms"]["t_match_ms"]
     achieved = head["match_bytes"] / (t_match * 1e-3) / 1e9 if t_match > 0 else None
     roofline = {
-        "kernel": f"k_match{'32' if head_name == 'fp32' else '64'}",
+        "kernel": f"k_filter<{'FP32' if head_name == 'fp32' else 'FP64'}>",
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
@@ -136,6 +221,15 @@ def main():
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": None,
     }
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    extra = {}
+    if "quad" in forms:
+        extra["quad_direction"] = bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, head["n_pairs"])
+    if "batch" in forms:
+        del a_ra, a_dec, b_ra, b_dec, out, sep
+        torch.cuda.empty_cache()
+        extra["batch"] = bench_batch(hlc, torch, dev, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -182,6 +276,7 @@ def main():
                       "zones": v["n_zones"]}
                   for k, v in results.items()},
     }
+    line["forms"].update(extra)
     print(json.dumps(line), flush=True)
 
 

@@ -69,7 +69,8 @@ typedef struct {
 /* opts->flags */
 #define HLC_NO_SEP 0x1u   /* do not write separations (out_sep may be NULL)    */
 #define HLC_PROFILE 0x2u  /* time each stage with HIP events (hlc_last_stats)  */
-#define HLC_SORTED 0x4u   /* reserved: sorted output is not implemented        */
+#define HLC_SORTED 0x4u   /* pairs (and separations) ordered by (a, b); not   *
+                           * with hlc_xmatch_stream (HLC_E_UNSUPPORTED)       */
 #define HLC_SELF 0x8u     /* self-match: B is the same arrays as A; each       *
                            * unordered pair is reported once as (i, j), i < j, *
                            * and (i, i) never (the self-match data sets of     *
@@ -78,7 +79,7 @@ typedef struct {
 /* Optional fixed tuning; zero fields mean "choose automatically". */
 typedef struct hlc_tuning {
   double zone_height_arcsec; /* Dec zone height; >= 2.0001 r is enforced       */
-  int32_t ra_cell_bins_log2; /* log2 of RA bins per FP32 cell (0 = auto)       */
+  int32_t ra_bins_log2;      /* log2 of RA bins per zone, 1..30 (0 = auto)     */
   int32_t reserved0;
   double zone_height_factor; /* batched form: scale of each job's density-     *
                               * derived zone height (0 = autotuned and cached)  */
@@ -105,7 +106,9 @@ typedef struct hlc_stats {
   int32_t n_zones;           /* Dec zones                                      */
   int32_t ra_bits;           /* RA bins = 2^ra_bits                            */
   double zone_height_arcsec;
-  /* stage times in milliseconds (HLC_PROFILE only, else 0) */
+  /* stage times in milliseconds (HLC_PROFILE only, else 0): t_match_ms is
+   * the filter kernel alone; t_certify_ms the candidate certification, the
+   * band list and the packing of the output */
   double t_keygen_ms, t_sort_ms, t_layout_ms, t_ranges_ms, t_match_ms, t_certify_ms, t_total_ms;
   double reserved[8];
 } hlc_stats;

@@ -38,6 +38,9 @@ struct Device {
   Counters* cnt = nullptr;        // device
   Counters* cnt_host = nullptr;   // pinned host mirror
   hipEvent_t ev[12] = {};
+  // staging sizes that earlier calls needed (grow-only), so a repeated
+  // workload does not pay the overflow re-run again
+  uint64_t hint_stage = 0, hint_cand = 0;
 };
 
 Device g_dev[MAX_DEVICES];
@@ -136,7 +139,7 @@ void set_radius(Geom& g, double r_arcsec) {
 
 // Partition geometry: zone height h_as (arcsec; <= 0 = automatic from the
 // catalogue sizes), radius r (halo and windows).
-Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int cell_log2) {
+Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits) {
   Geom g;
   set_radius(g, r_arcsec);
   if (!(h_as > 0)) {
@@ -153,20 +156,20 @@ Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int cell_lo
   g.h_deg = h;
   g.inv_h = 1.0 / h;
   g.nz = (int32_t)nz;
-  g.rb = std::min(30, 32 - ceil_log2((uint64_t)nz));
+  const int zb = ceil_log2((uint64_t)nz);
+  const int rb_max = std::min(30, 32 - zb);
+  if (ra_bits > 0) {
+    g.rb = std::min(ra_bits, rb_max);
+  } else {
+    // bins about h/8 wide at the equator keep the RA windows tight; the key
+    // then takes every bit of the 8-bit radix digits it needs anyway
+    int need = (int)std::ceil(std::log2(360.0 * 8.0 / h));
+    need = std::min(std::max(need, 1), rb_max);
+    const int digits = (zb + need + 7) / 8;
+    g.rb = std::min(8 * digits - zb, rb_max);
+  }
   g.nbins = 1u << g.rb;
   g.bin_scale = (double)g.nbins / 360.0;
-  int sb;
-  if (cell_log2 > 0) {
-    sb = std::max(0, g.rb - cell_log2);
-  } else {
-    // FP32 cells: RA extent comparable to the zone height
-    double want = 360.0 / h;
-    sb = std::min(std::max(0, (int)std::lround(std::log2(std::max(1.0, want)))), std::min(g.rb, 20));
-  }
-  g.cell_shift = g.rb - sb;
-  g.nsuper = 1u << sb;
-  g.pad_ = 0;
   return g;
 }
 
@@ -174,6 +177,7 @@ int key_bits(const Geom& g) { return ceil_log2((uint64_t)g.nz) + g.rb; }
 
 struct Thresholds {
   double c_r, t_lo64, t_hi64, H_lo, H_hi;
+  float thr32;
 };
 
 Thresholds thresholds(double r_arcsec) {
@@ -188,6 +192,14 @@ Thresholds thresholds(double r_arcsec) {
   const double H = s * s;
   t.H_lo = H * (1.0 - EPS_BAND);
   t.H_hi = H * (1.0 + EPS_BAND);
+  // FP32 filter on FP32 unit vectors: (c_r (1 + 8u) + 3.5 (v + 5u))^2 (1 + 6v),
+  // rounded up (the derivation is with the match kernels)
+  const double v = 0x1p-24;
+  const double c32 = t.c_r * (1.0 + 8.0 * U64) + 3.5 * (v + 5.0 * U64);
+  const double T = c32 * c32 * (1.0 + 6.0 * v);
+  float Tf = (float)T;
+  if ((double)Tf < T) Tf = std::nextafter(Tf, INFINITY);
+  t.thr32 = Tf;
   return t;
 }
 
@@ -195,7 +207,7 @@ int check_opts(const hlc_opts* o) {
   if (!o || !o->n_pairs) return HLC_E_INVAL;
   if (o->capacity < 0) return HLC_E_INVAL;
   if (o->precision != HLC_FP32_RECHECK && o->precision != HLC_FP64) return HLC_E_INVAL;
-  if (o->flags & HLC_SORTED) return HLC_E_UNSUPPORTED;
+  if (o->tuning && (o->tuning->ra_bins_log2 < 0 || o->tuning->ra_bins_log2 > 30)) return HLC_E_INVAL;
   return HLC_OK;
 }
 
@@ -209,7 +221,7 @@ int check_common(double r_arcsec, int64_t na, int64_t nb, const hlc_opts* o) {
 double tuned_height(const hlc_opts* o) {
   return (o->tuning && o->tuning->zone_height_arcsec > 0) ? o->tuning->zone_height_arcsec : 0.0;
 }
-int tuned_cells(const hlc_opts* o) { return o->tuning ? o->tuning->ra_cell_bins_log2 : 0; }
+int tuned_bins(const hlc_opts* o) { return o->tuning ? o->tuning->ra_bins_log2 : 0; }
 
 // One partitioned catalogue.
 struct Side {
@@ -219,12 +231,9 @@ struct Side {
   Rec64* r64 = nullptr;
   Rec32* r32 = nullptr;
   double2* radec = nullptr;
+  Rec64* src64 = nullptr;     // per-source records written by the keygen
+  SrcRec32* src32 = nullptr;  // (nullptr: the layout gathers (ra, dec))
   const double *ra = nullptr, *dec = nullptr;  // original coordinates (for the band list)
-};
-
-struct Tables {
-  double2* zone_cs = nullptr;
-  double2* super_cs = nullptr;
 };
 
 // keygen -> sort -> layout for one catalogue. The side's buffers hold n
@@ -240,20 +249,30 @@ void mark(Device& dev, int slot, hipStream_t s) {
 }
 
 int partition(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
-              bool l64, bool l32, const Tables& tb, const SortScratch& sc, uint32_t err_bit, Side& sd,
+              bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd,
               const Slots& sl, hipStream_t s) {
   sd.n_src = n;
   sd.ra = ra;
   sd.dec = dec;
-  launch_keygen(ra, dec, n, g, halo, err_bit, sd.keys, sd.vals, dev.cnt, s);
+  // an odd number of radix passes ends in the scratch pair unless it starts there
+  const int bits = key_bits(g);
+  const bool from_alt = (radix_passes(bits) & 1) != 0;
+  launch_keygen(ra, dec, n, g, halo, err_bit, from_alt ? sc.keys_alt : sd.keys, from_alt ? sc.vals_alt : sd.vals,
+                dev.cnt, s, l64 ? sd.src64 : nullptr, l32 ? sd.src32 : nullptr);
   mark(dev, sl.keygen, s);
   sd.n_cap = halo ? 2 * n : n;
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
   mark(dev, sl.sort_begin, s);
-  radix_sort(sd.keys, sd.vals, sd.cnt, key_bits(g), sc, s);
+  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt);
   mark(dev, sl.sort, s);
-  if (l64) launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
-  if (l32) launch_layout32(sd.keys, sd.vals, sd.cnt, ra, dec, g, tb.zone_cs, tb.super_cs, sd.r32, sd.radec, s);
+  if (l64) {
+    if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
+    else launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
+  }
+  if (l32) {
+    if (sd.src32) launch_gather32(sd.vals, sd.cnt, sd.src32, sd.r32, sd.radec, s);
+    else launch_layout32(sd.vals, sd.cnt, ra, dec, sd.r32, sd.radec, s);
+  }
   mark(dev, sl.layout, s);
   return HLC_OK;
 }
@@ -271,13 +290,15 @@ struct MatchWs {
   Regions reg;
 };
 
-// Sizes of the two spill-prone work buffers of a call: the band list and
-// the staging slots per output region. Both start from estimates; a call
-// whose counts exceed them runs again with the counted sizes (the counts
-// are deterministic, so the second run fits).
+// Sizes of the spill-prone work buffers of a call: the band list, the pair
+// slots per output region and the candidate slots per candidate region (0:
+// candidates are not staged). All start from estimates; a call whose counts
+// exceed them runs again with the counted sizes (the counts are
+// deterministic, so the second run fits).
 struct Caps {
   uint64_t band;
   uint64_t stage;
+  uint64_t cand;
 };
 
 uint64_t stage_guess(uint64_t cap) {
@@ -285,26 +306,41 @@ uint64_t stage_guess(uint64_t cap) {
   return std::min<uint64_t>(s, 1ull << 22);
 }
 
-Caps initial_caps(uint64_t entries, uint64_t cap) { return Caps{(1u << 20) + entries / 64, stage_guess(cap)}; }
-
-void carve_regions(Carve& c, Regions& r, uint64_t S, bool sep) {
-  r.fill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
-  r.cand = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
-  r.S = S;
-  r.pairs = c.take<uint2>((size_t)NREG * S);
-  r.sep = sep ? c.take<double>((size_t)NREG * S) : nullptr;
+Caps initial_caps(const Device& d, uint64_t entries, uint64_t cap, bool stage_cand) {
+  Caps k;
+  k.band = (1u << 20) + entries / 64;
+  k.stage = std::max(stage_guess(cap), d.hint_stage);
+  k.cand = stage_cand ? std::max(std::min<uint64_t>(entries / (2 * NREG) + 4096, 1ull << 22), d.hint_cand) : 0;
+  return k;
 }
 
-// True when the call must run again: its band list overflowed, or an output
-// region overflowed although the caller's buffer holds every pair.
-bool regrow(const Counters& h, uint64_t cap, Caps& k) {
+void carve_regions(Carve& c, Regions& r, const Caps& k, bool sep) {
+  r.fill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
+  r.cfill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
+  r.S = k.stage;
+  r.pairs = c.take<uint2>((size_t)NREG * k.stage);
+  r.sep = sep ? c.take<double>((size_t)NREG * k.stage) : nullptr;
+  r.Sc = k.cand;
+  r.cand = k.cand ? c.take<uint2>((size_t)NREG * k.cand) : nullptr;
+}
+
+// True when the call must run again: its band list overflowed, a candidate
+// region overflowed, or a pair region overflowed although the caller's
+// buffer holds every pair.
+bool regrow(Device& d, const Counters& h, uint64_t cap, Caps& k) {
   bool again = false;
   if (h.n_band > k.band) {
     k.band = h.n_band + h.n_band / 4 + 1024;
     again = true;
   }
-  if (h.n_pairs <= cap && h.region_max > k.stage) {
-    k.stage = h.region_max + 1024;
+  if (k.cand && h.cand_max > k.cand) {
+    k.cand = h.cand_max + h.cand_max / 8 + 1024;
+    d.hint_cand = std::max(d.hint_cand, k.cand);
+    again = true;
+  }
+  if (!again && h.n_pairs <= cap && h.region_max > k.stage) {
+    k.stage = h.region_max + h.region_max / 8 + 1024;
+    d.hint_stage = std::max(d.hint_stage, k.stage);
     again = true;
   }
   return again;
@@ -326,17 +362,17 @@ OutArgs out_args(hlc_pair* pairs, double* sep, uint64_t cap, uint2* band, uint64
 
 // Everything after the partition: ranges, match, certification.
 void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_arcsec, bool fp32,
-           bool skip_halo_a, bool self_only, const Radii& rad, const Tables& tb, const MatchWs& w,
+           bool skip_halo_a, bool self_only, const Radii& rad, const MatchWs& w,
            hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, hipStream_t s) {
   Thresholds th = thresholds(r_arcsec);
-  launch_zone_tables(g, w.zmarg, tb.zone_cs, nullptr, s);
+  launch_zone_tables(g, w.zmarg, s);
   const uint32_t* zstart = w.zstartB;
   if (!zstart) {
     launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, s);
     zstart = w.zstart_buf;
   }
   launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, w.lb, s);
-  launch_ranges(A.keys, A.cnt, w.lb, B.keys, zstart, w.zmarg, g, th.c_r, w.ranges, s);
+  launch_ranges(A.keys, A.cnt, w.lb, B.keys, zstart, w.zmarg, g, w.ranges, s);
   if (prof) (void)hipEventRecord(dev.ev[8], s);
   MatchArgs ma{};
   ma.ranges = w.ranges;
@@ -351,8 +387,7 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.radecB = B.radec;
   ma.keysA = A.keys;
   ma.keysB = B.keys;
-  ma.zone_cs = tb.zone_cs;
-  ma.super_cs = tb.super_cs;
+  ma.thr32 = th.thr32;
   ma.geom = g;
   ma.H_lo = th.H_lo;
   ma.H_hi = th.H_hi;
@@ -364,9 +399,9 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.hp_order = -1;
   const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
   launch_regions_reset(oa, s);
-  if (fp32) launch_match32(ma, oa, s);
-  else launch_match64(ma, oa, s);
+  launch_filter(ma, oa, fp32, s);
   if (prof) (void)hipEventRecord(dev.ev[9], s);
+  launch_cand(ma, oa, fp32, s);
   launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, s);
   launch_compact(oa, s);
   if (prof) (void)hipEventRecord(dev.ev[10], s);
@@ -383,17 +418,20 @@ size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, 
   w.zstartB = nullptr;
   w.band = c.take<uint2>(band_cap);
   w.band_cap = band_cap;
-  carve_regions(c, w.reg, caps.stage, true);
+  carve_regions(c, w.reg, caps, true);
   return c.off;
 }
 
-void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32) {
+// cap entries; n_src > 0 also carves the per-source records of the keygen
+void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src = 0) {
   cap = std::max(cap, 1u);
   sd.keys = c.take<uint32_t>(cap);
   sd.vals = c.take<uint32_t>(cap);
   sd.r64 = l64 ? c.take<Rec64>(cap) : nullptr;
   sd.r32 = l32 ? c.take<Rec32>(cap) : nullptr;
   sd.radec = l32 ? c.take<double2>(cap) : nullptr;
+  sd.src64 = (l64 && n_src) ? c.take<Rec64>(n_src) : nullptr;
+  sd.src32 = (l32 && n_src) ? c.take<SrcRec32>(n_src) : nullptr;
 }
 
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {
@@ -401,13 +439,9 @@ void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {
   sc.keys_alt = c.take<uint32_t>(nmax);
   sc.vals_alt = c.take<uint32_t>(nmax);
   sc.counts = c.take<uint32_t>(sort_counts_len(nmax));
-  sc.block_sums = c.take<uint32_t>(sort_block_sums_len(nmax));
+  sc.digit_totals = c.take<uint32_t>(sort_digit_totals_len(nmax));
 }
 
-void carve_tables(Carve& c, Tables& tb, const Geom& g, bool l32) {
-  tb.zone_cs = c.take<double2>((size_t)g.nz);
-  tb.super_cs = l32 ? c.take<double2>((size_t)g.nsuper) : nullptr;
-}
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
@@ -464,20 +498,18 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   const bool prof = (o->flags & HLC_PROFILE) != 0;
   const bool fp32 = o->precision == HLC_FP32_RECHECK;
   const bool self = (o->flags & HLC_SELF) != 0;
-  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_cells(o));
+  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o));
   const uint32_t nB = (uint32_t)nb;
   // self-match: A's entries are B's (halo copies included)
   const uint32_t nA = self ? 2 * nB : (uint32_t)na;
 
   Side A, B;
   SortScratch sc;
-  Tables tb;
   MatchWs w;
   auto lay = [&](Carve& c) {
-    if (!self) carve_side(c, A, nA, !fp32, fp32);
-    carve_side(c, B, 2 * nB, !fp32, fp32);
+    if (!self) carve_side(c, A, nA, !fp32, fp32, nA);
+    carve_side(c, B, 2 * nB, !fp32, fp32, nB);
     carve_sort(c, sc, std::max(nA, 2 * nB));
-    carve_tables(c, tb, g, fp32);
     carve_match_ws(c, w, nA, g, caps, true);
   };
   Carve sizing{nullptr};
@@ -488,20 +520,19 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
 
   if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
   launch_zero_counters(dev->cnt, s);
-  if (fp32) launch_zone_tables(g, w.zmarg, tb.zone_cs, tb.super_cs, s);
   // B first: its halo count is read back before its sort; A's keygen and
   // sort then queue behind it without another synchronisation.
   const Slots slB = prof ? Slots{1, 2, 3, 4} : NO_SLOTS;
   const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
-  HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, tb, sc, 2u, B, slB, s));
+  HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s));
   if (self) {
     // one partition serves both roles; its halo copies are skipped as A
     for (int k : {slA.keygen, slA.sort, slA.layout}) mark(*dev, k, s);
     A = B;
   } else {
-    HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, tb, sc, 1u, A, slA, s));
+    HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, sc, 1u, A, slA, s));
   }
-  match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, tb, w, out_pairs,
+  match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, w, out_pairs,
         (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, s);
   HLC_CHECK(read_counters(*dev, s, prof));
 
@@ -510,7 +541,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     *o->n_pairs = 0;
     return HLC_E_INVAL;
   }
-  if (regrow(h, (uint64_t)o->capacity, caps)) {
+  if (regrow(*dev, h, (uint64_t)o->capacity, caps)) {
     *again = true;
     return HLC_OK;
   }
@@ -524,7 +555,9 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
 int xmatch_core(const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
                 const double* b_dec, int64_t nb, double r_arcsec, hlc_pair* out_pairs,
                 double* out_sep, const hlc_opts* o, const Radii& rad = Radii{nullptr, nullptr, 0.0}) {
-  Caps caps = initial_caps((uint64_t)(na + nb), (uint64_t)o->capacity);
+  Device* dev = nullptr;
+  HLC_CHECK(get_device(&dev));
+  Caps caps = initial_caps(*dev, (uint64_t)(na + nb), (uint64_t)o->capacity, true);
   for (int attempt = 0; attempt < 3; ++attempt) {
     bool again = false;
     int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, caps, &again, rad);
@@ -554,6 +587,42 @@ int validate_only(const double* a_ra, const double* a_dec, int64_t na, const dou
   return dev->cnt_host->err ? HLC_E_INVAL : HLC_OK;
 }
 
+int bits_for(int64_t n) { return std::max(1, ceil_log2((uint64_t)std::max<int64_t>(n, 2))); }
+
+// HLC_SORTED: the call's pairs, already in the caller's buffers, ordered by
+// (a, b) (indices below na and nb).
+int sort_output(int st, hlc_pair* pairs, double* sep, const hlc_opts* o, int64_t na, int64_t nb) {
+  if (st != HLC_OK || !(o->flags & HLC_SORTED)) return st;
+  const int64_t n = *o->n_pairs;
+  if (n <= 1) return HLC_OK;
+  if (n >= (int64_t(1) << 31)) return HLC_E_UNSUPPORTED;
+  if (o->flags & HLC_NO_SEP) sep = nullptr;
+  Device* dev = nullptr;
+  HLC_CHECK(get_device(&dev));
+  hipStream_t s = (hipStream_t)o->stream;
+  const uint32_t m = (uint32_t)n;
+  uint32_t *keys = nullptr, *vals = nullptr;
+  uint2* tp = nullptr;
+  double* ts = nullptr;
+  SortScratch sc;
+  auto lay = [&](Carve& c) {
+    keys = c.take<uint32_t>(m);
+    vals = c.take<uint32_t>(m);
+    carve_sort(c, sc, m);
+    tp = c.take<uint2>(m);
+    ts = sep ? c.take<double>(m) : nullptr;
+  };
+  Carve sz{nullptr};
+  lay(sz);
+  HLC_CHECK(ensure_ws(*dev, sz.off + 256));
+  Carve c{(char*)dev->ws};
+  lay(c);
+  sort_pairs(reinterpret_cast<uint2*>(pairs), sep, m, bits_for(na), bits_for(nb), keys, vals, tp, ts, sc, s);
+  HLC_TRY(hipStreamSynchronize(s));
+  HLC_TRY(hipGetLastError());
+  return HLC_OK;
+}
+
 }  // namespace
 }  // namespace hlc
 
@@ -565,7 +634,6 @@ struct hlc_part {
   double r_build = 0;
   void* mem = nullptr;
   hlc::Side side;
-  hlc::Tables tb;
   uint32_t* zstart = nullptr;
   double* ra = nullptr;  // private copies of the coordinates
   double* dec = nullptr;
@@ -586,7 +654,8 @@ int hlc_xmatch(const double* a_ra, const double* a_dec, int64_t na, const double
   if ((opts->flags & HLC_SELF) && (a_ra != b_ra || a_dec != b_dec || na != nb)) return HLC_E_INVAL;
   try {
     if (na == 0 || nb == 0) return validate_only(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, opts);
-    return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep_arcsec, opts);
+    return sort_output(xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep_arcsec, opts),
+                       out_pairs, out_sep_arcsec, opts, na, nb);
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {
@@ -628,8 +697,9 @@ int hlc_xmatch_radii(const double* a_ra, const double* a_dec, const double* a_er
     // all errors zero: only identical positions match; any positive filter
     // radius finds them
     rmax = std::max(rmax, 1e-6);
-    return xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, rmax, out_pairs, out_sep_arcsec, opts,
-                       Radii{a_err, b_err, k_sigma});
+    return sort_output(xmatch_core(a_ra, a_dec, na, b_ra, b_dec, nb, rmax, out_pairs, out_sep_arcsec, opts,
+                                   Radii{a_err, b_err, k_sigma}),
+                       out_pairs, out_sep_arcsec, opts, na, nb);
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {
@@ -654,7 +724,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
     HLC_CHECK(get_device(&dev));
     hipStream_t s = (hipStream_t)opts->stream;
     const uint32_t capA = 5u * (uint32_t)na, capB = 5u * (uint32_t)nb;
-    Caps caps = initial_caps((uint64_t)capA + capB, (uint64_t)opts->capacity);
+    Caps caps = initial_caps(*dev, (uint64_t)capA + capB, (uint64_t)opts->capacity, true);
     for (int attempt = 0; attempt < 3; ++attempt) {
       Side A, B;
       SortScratch sc;
@@ -710,13 +780,14 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       const OutArgs oa = out_args(out_pairs, (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec,
                                   (uint64_t)opts->capacity, w.band, w.band_cap, w.reg, dev->cnt);
       launch_regions_reset(oa, s);
-      launch_match64(ma, oa, s);
+      launch_filter(ma, oa, false, s);
+      launch_cand(ma, oa, false, s);
       launch_certify(a_ra, a_dec, b_ra, b_dec, r_arcsec, th.H_lo, th.H_hi, Radii{nullptr, nullptr, 0.0}, oa, s);
       launch_compact(oa, s);
       HLC_CHECK(read_counters(*dev, s, false));
       const Counters& h = *dev->cnt_host;
       if (h.err) return HLC_E_INVAL;
-      if (regrow(h, (uint64_t)opts->capacity, caps)) continue;
+      if (regrow(*dev, h, (uint64_t)opts->capacity, caps)) continue;
       std::memset(&g_stats, 0, sizeof(g_stats));
       g_stats.na = na;
       g_stats.nb = nb;
@@ -726,7 +797,8 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       g_stats.n_band = (int64_t)h.n_band;
       g_stats.n_ties = (int64_t)h.n_ties;
       *opts->n_pairs = (int64_t)h.n_pairs;
-      return h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK;
+      return sort_output(h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK, out_pairs,
+                         out_sep_arcsec, opts, na, nb);
     }
     return HLC_E_NOMEM;
   } catch (const std::bad_alloc&) {
@@ -744,7 +816,6 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
   if (!(r_arcsec > 0.0) || !(r_arcsec <= 3600.0)) return HLC_E_INVAL;
   if (n < 0 || n >= (int64_t(1) << 31)) return HLC_E_INVAL;
   if (n > 0 && (!ra_deg || !dec_deg)) return HLC_E_INVAL;
-  if (opts->flags & HLC_SORTED) return HLC_E_UNSUPPORTED;
   try {
     Device* dev = nullptr;
     int dev_id = 0;
@@ -757,11 +828,10 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     auto* p = new hlc_part();
     p->device = dev_id;
     p->r_build = r_arcsec;
-    p->g = make_geom(r_arcsec, h_as, n, n, tuned_cells(opts));
+    p->g = make_geom(r_arcsec, h_as, n, n, tuned_bins(opts));
     const uint32_t nn = (uint32_t)n, cap = 2 * nn;
     auto lay = [&](Carve& c) {
       carve_side(c, p->side, cap, true, true);
-      carve_tables(c, p->tb, p->g, true);
       p->zstart = c.take<uint32_t>((size_t)p->g.nz + 1);
       p->ra = c.take<double>(std::max(nn, 1u));
       p->dec = c.take<double>(std::max(nn, 1u));
@@ -775,24 +845,31 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     }
     Carve c{(char*)p->mem};
     lay(c);
-    // sort scratch comes from the shared workspace
+    // sort scratch and the keygen's per-source records come from the shared
+    // workspace (the part keeps only the sorted entries)
     SortScratch sc;
+    auto scratch = [&](Carve& c) {
+      carve_sort(c, sc, std::max(cap, 1u));
+      p->side.src64 = c.take<Rec64>(std::max(nn, 1u));
+      p->side.src32 = c.take<SrcRec32>(std::max(nn, 1u));
+    };
     Carve ss{nullptr};
-    carve_sort(ss, sc, std::max(cap, 1u));
+    scratch(ss);
     st = ensure_ws(*dev, ss.off + 256);
     if (st) {
       hlc_part_free(p);
       return st;
     }
     Carve cs{(char*)dev->ws};
-    carve_sort(cs, sc, std::max(cap, 1u));
+    scratch(cs);
     if (nn) {
       HLC_TRY(hipMemcpyAsync(p->ra, ra_deg, (size_t)nn * 8, hipMemcpyDeviceToDevice, s));
       HLC_TRY(hipMemcpyAsync(p->dec, dec_deg, (size_t)nn * 8, hipMemcpyDeviceToDevice, s));
     }
     launch_zero_counters(dev->cnt, s);
-    launch_zone_tables(p->g, nullptr, p->tb.zone_cs, p->tb.super_cs, s);
-    st = partition(*dev, p->ra, p->dec, nn, p->g, true, true, true, p->tb, sc, 1u, p->side, NO_SLOTS, s);
+    st = partition(*dev, p->ra, p->dec, nn, p->g, true, true, true, sc, 1u, p->side, NO_SLOTS, s);
+    p->side.src64 = nullptr;
+    p->side.src32 = nullptr;
     if (st == HLC_OK) {
       launch_zone_starts(p->side.keys, p->side.cnt, p->g, p->zstart, s);
       st = read_counters(*dev, s, false);
@@ -830,7 +907,7 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
   if (!A || !B) return HLC_E_INVAL;
   HLC_CHECK(check_opts(opts));
   if (!(r_arcsec > 0.0) || !(r_arcsec <= B->r_build)) return HLC_E_INVAL;
-  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb || A->g.cell_shift != B->g.cell_shift)
+  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb)
     return HLC_E_INVAL;
   if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
     return HLC_E_INVAL;
@@ -849,7 +926,7 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       std::memset(&g_stats, 0, sizeof(g_stats));
       return HLC_OK;
     }
-    Caps caps = initial_caps((uint64_t)A->side.cnt.cap + B->side.cnt.cap, (uint64_t)opts->capacity);
+    Caps caps = initial_caps(*dev, (uint64_t)A->side.cnt.cap + B->side.cnt.cap, (uint64_t)opts->capacity, true);
     for (int attempt = 0; attempt < 3; ++attempt) {
       MatchWs w;
       Carve sizing{nullptr};
@@ -860,16 +937,17 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       w.zstartB = B->zstart;
       if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
       launch_zero_counters(dev->cnt, s);
-      match(*dev, A->side, B->side, g, r_arcsec, fp32, true, false, Radii{nullptr, nullptr, 0.0}, A->tb, w,
+      match(*dev, A->side, B->side, g, r_arcsec, fp32, true, false, Radii{nullptr, nullptr, 0.0}, w,
             out_pairs,
             (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec, (uint64_t)opts->capacity, prof, s);
       HLC_CHECK(read_counters(*dev, s, prof));
       const Counters& h = *dev->cnt_host;
-      if (regrow(h, (uint64_t)opts->capacity, caps)) continue;
+      if (regrow(*dev, h, (uint64_t)opts->capacity, caps)) continue;
       fill_stats(h, A->side.n_src, B->side.n_src, B->side.cnt.cap, g);
       if (prof) fill_times(*dev, false);
       *opts->n_pairs = (int64_t)h.n_pairs;
-      return h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK;
+      return sort_output(h.n_pairs > (unsigned long long)opts->capacity ? HLC_E_OVERFLOW : HLC_OK, out_pairs,
+                         out_sep_arcsec, opts, A->side.n_src, B->side.n_src);
     }
     return HLC_E_NOMEM;
   } catch (const std::bad_alloc&) {
@@ -1060,7 +1138,7 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Ca
   b.band = c.take<uint2>(band_cap);
   b.band_job = c.take<uint32_t>(band_cap);
   b.band_cap = band_cap;
-  carve_regions(c, b.reg, caps.stage, true);
+  carve_regions(c, b.reg, caps, true);
   b.jcount = own_jcount ? c.take<unsigned long long>(std::max(P.njobs, 1)) : nullptr;
 }
 
@@ -1199,7 +1277,7 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
 
   unsigned long long* jcount = reinterpret_cast<unsigned long long*>(job_pair_count);
   const uint64_t cap = (uint64_t)o->capacity;
-  Caps caps = initial_caps((uint64_t)(P.NA + P.NB), cap);
+  Caps caps = initial_caps(*dev, (uint64_t)(P.NA + P.NB), cap, false);
   double* sep = (o->flags & HLC_NO_SEP) ? nullptr : out_sep;
 
   // zone-height factor: given, cached, or tuned now (eager timed runs)
@@ -1272,7 +1350,7 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
       *o->n_pairs = 0;
       return HLC_E_INVAL;
     }
-    if (regrow(h, cap, caps)) {
+    if (regrow(*dev, h, cap, caps)) {
       drop_graph(BS);
       continue;
     }
@@ -1309,7 +1387,9 @@ int hlc_xmatch_batch(const hlc_job* jobs, int32_t njobs, const double* a_ra, con
   if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
     return HLC_E_INVAL;
   try {
-    return batch_impl(jobs, njobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep_arcsec, job_pair_count, opts);
+    return sort_output(
+        batch_impl(jobs, njobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep_arcsec, job_pair_count, opts),
+        out_pairs, out_sep_arcsec, opts, int64_t(1) << 31, int64_t(1) << 31);
   } catch (const std::bad_alloc&) {
     return HLC_E_NOMEM;
   } catch (...) {
@@ -1660,7 +1740,7 @@ int hlc_xmatch_stream(const double* a_ra_host, const double* a_dec_host, int64_t
   if (!sink) return HLC_E_INVAL;
   if ((na > 0 && (!a_ra_host || !a_dec_host)) || (nb > 0 && (!b_ra_host || !b_dec_host)))
     return HLC_E_INVAL;
-  if (opts->flags & HLC_SELF) return HLC_E_UNSUPPORTED;
+  if (opts->flags & (HLC_SELF | HLC_SORTED)) return HLC_E_UNSUPPORTED;  // pairs arrive per chunk
   try {
     return stream_impl(a_ra_host, a_dec_host, na, b_ra_host, b_dec_host, nb, r_arcsec, sink, user, opts);
   } catch (const std::bad_alloc&) {

@@ -458,8 +458,7 @@ __global__ __launch_bounds__(256) void k_batch_ranges(const uint32_t* __restrict
     if (t < n) work += e_[t] - s_[t];
   }
   R.count = (uint32_t)n;
-  R.thr32 = 0.0f;
-  R.pad_[0] = R.pad_[1] = 0u;
+  R.pad_[0] = R.pad_[1] = R.pad_[2] = 0u;
   out[grp] = R;
   // LPT order: most B work first (ascending sort of the complement)
   cost_key[grp] = 0xfffffffeu - min(work + 1u, 0xfffffffeu);

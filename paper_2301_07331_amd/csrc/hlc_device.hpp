@@ -22,8 +22,7 @@ constexpr int GROUP = 16;                             // A sources per group (on
 constexpr int MAXR = 4;                               // B ranges kept per group
 
 // Partition geometry of one call: Dec zones of height h, RA bins of width
-// 360/nbins; a source's key is (zone << rb) | bin. FP32 cells are
-// (zone, bin >> cell_shift).
+// 360/nbins; a source's key is (zone << rb) | bin.
 struct Geom {
   double h_deg;       // zone height (deg)
   double inv_h;       // 1 / h_deg
@@ -33,9 +32,6 @@ struct Geom {
   int32_t nz;         // number of zones
   int32_t rb;         // RA bits; nbins = 1 << rb
   uint32_t nbins;
-  int32_t cell_shift; // FP32 cell = bin >> cell_shift
-  uint32_t nsuper;    // nbins >> cell_shift
-  int32_t pad_;
 };
 
 // An entry count known on the host (base) plus an optional count that only
@@ -57,8 +53,7 @@ struct GroupRanges {
   uint32_t start[MAXR];
   uint32_t end[MAXR];
   uint32_t count;
-  float thr32;        // FP32 chord^2 acceptance threshold for this group
-  uint32_t pad_[2];
+  uint32_t pad_[3];
 };
 
 // Device-side counters, read back once per call.
@@ -71,17 +66,22 @@ struct Counters {
   unsigned int err;               // bit 0: bad coordinate in A, bit 1: in B
   unsigned int queue;             // work-queue head of persistent kernels
   unsigned long long aux[2];      // entry counts of multi-entry keygens (A, B)
-  unsigned long long region_max;  // largest output-region fill (compaction)
-  unsigned long long pad_;
+  unsigned long long region_max;  // largest pair-region fill (compaction)
+  unsigned long long cand_max;    // largest candidate-region fill
 };
 
 struct Rec64 {      // FP64 working record (32 B)
   double x, y, z;
   uint32_t idx, pad;
 };
-struct Rec32 {      // FP32 working record (16 B): offset from the cell centre
+struct Rec32 {      // FP32 working record (16 B): the FP32 unit vector (single
+  float x, y, z;    // calls) or its offset from the job's frame centre (batched form)
+  uint32_t idx;
+};
+struct SrcRec32 {   // per-source FP32 record with its FP64 position (32 B)
   float x, y, z;
   uint32_t idx;
+  double ra, dec;
 };
 
 // ---------------------------------------------------------------------------

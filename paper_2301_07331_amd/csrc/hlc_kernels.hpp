@@ -13,35 +13,48 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void launch_zero_counters(Counters* c, hipStream_t s);
 // keys/vals for A (one entry per source, or one per source plus Dec-halo
 // copies appended after n when `halo` is set).
+// keys (and halo copies) of n sources; with src64 / src32 also each
+// source's working record in input order, for launch_gather64 / 32
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
-                   uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s);
+                   uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
+                   Rec64* src64 = nullptr, SrcRec32* src32 = nullptr);
+void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s);
+void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* src, Rec32* rec, double2* radec,
+                     hipStream_t s);
 
 struct SortScratch {
   uint32_t* keys_alt;
   uint32_t* vals_alt;
   uint32_t* counts;     // 256 * ntiles
-  uint32_t* block_sums; // scan partials
+  uint32_t* digit_totals; // per-digit totals of one pass
 };
 size_t sort_counts_len(uint32_t n);
-size_t sort_block_sums_len(uint32_t n);
+size_t sort_digit_totals_len(uint32_t n);
 // LSD radix sort of (keys, vals), ascending, stable, on key bits [0, key_bits).
 // The result ends in (keys, vals).
+// Stable LSD sort of (keys, vals) by the low key_bits bits; the result is
+// in (keys, vals). With from_alt the input is in the scratch pair instead:
+// callers that write their input there when radix_passes(key_bits) is odd
+// spare the final copy.
+int radix_passes(int key_bits);
+// n output pairs (and their separations, if sep) ordered by (a, b); keys,
+// vals, tmp_pairs, tmp_sep hold n entries each
+void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, uint32_t* keys, uint32_t* vals,
+                uint2* tmp_pairs, double* tmp_sep, const SortScratch& sc, hipStream_t s);
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
-                hipStream_t s);
+                hipStream_t s, bool from_alt = false);
 
-void launch_zone_tables(const Geom& g, int32_t* zmarg, double2* zone_cs, double2* super_cs,
-                        hipStream_t s);
+void launch_zone_tables(const Geom& g, int32_t* zmarg, hipStream_t s);
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s);
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s);
-void launch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,
-                     const double* dec, const Geom& g, const double2* zone_cs,
-                     const double2* super_cs, Rec32* rec, double2* radec, hipStream_t s);
+void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
+                     Rec32* rec, double2* radec, hipStream_t s);
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
                      const DevCount& nb, uint32_t* lb, hipStream_t s);
 void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
-                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g, double c_r,
+                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
                    GroupRanges* out, hipStream_t s);
 
 // ---- match.hip -------------------------------------------------------------
@@ -49,16 +62,18 @@ void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb
 // memory side (device-scope atomics on one address), so pairs are appended
 // to NREG striped staging regions instead (region = wave index mod NREG,
 // counters 256 B apart) and a compaction kernel packs the regions into the
-// caller's buffer in region order.
+// caller's buffer in region order. Filter candidates are staged the same way.
 constexpr int NREG = 256;
 constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
 
 struct Regions {
   unsigned long long* fill;     // NREG * REG_STRIDE; fill[k * REG_STRIDE] = pairs sent to region k
-  unsigned long long* cand;     // NREG * REG_STRIDE; certified candidates (statistics)
+  unsigned long long* cfill;    // NREG * REG_STRIDE; candidates sent to region k
   uint2* pairs;                 // NREG * S staging
   double* sep;                  // NREG * S staging, or nullptr
-  unsigned long long S;         // staging slots per region
+  unsigned long long S;         // pair slots per region
+  uint2* cand;                  // NREG * Sc staging of (A position, B position), or nullptr
+  unsigned long long Sc;        // candidate slots per region (0: candidates are only counted)
 };
 
 struct OutArgs {
@@ -108,7 +123,7 @@ __device__ inline void emit_one(uint32_t ia, uint32_t ib, double sep, const OutA
 }
 
 __device__ inline void count_candidates(uint32_t qn, const OutArgs& o) {
-  if (lane_id() == 0) atomicAdd(&o.reg.cand[wave_region() * REG_STRIDE], (unsigned long long)qn);
+  if (lane_id() == 0) atomicAdd(&o.reg.cfill[wave_region() * REG_STRIDE], (unsigned long long)qn);
 }
 
 struct MatchArgs {
@@ -118,15 +133,14 @@ struct MatchArgs {
   const Rec64* recA64;
   const Rec64* recB64;
   double t_lo64, t_hi64;        // chord^2: certain in / candidate
-  // FP32 form
+  // FP32 form: FP32 unit vectors and the FP64 (ra, dec) of every entry
   const Rec32* recA32;
   const Rec32* recB32;
   const double2* radecA;
   const double2* radecB;
+  float thr32;                  // chord^2 bound covering the FP32 rounding
   const uint32_t* keysA;
   const uint32_t* keysB;
-  const double2* zone_cs;
-  const double2* super_cs;
   Geom geom;
   double H_lo, H_hi;            // haversine: certain in / candidate (FP64 band)
   // A entries flagged as halo copies are skipped (partition reuse)
@@ -155,8 +169,10 @@ struct Radii {
 // (n_pairs, n_cand and region_max of *o.cnt are set by the packing)
 void launch_regions_reset(const OutArgs& o, hipStream_t s);
 void launch_compact(const OutArgs& o, hipStream_t s);
-void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s);
-void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s);
+// the filter writes candidates into the candidate regions; the
+// certification kernel decides them and writes pairs and the band list
+void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s);
+void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s);
 // Re-decide the band list from the original coordinates: FP64 haversine,
 // then double-double inside the FP64 band.
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,

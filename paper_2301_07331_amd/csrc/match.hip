@@ -2,24 +2,30 @@
 // module, sections 3.1 and 4.3.1), redesigned for CDNA4 wave64.
 //
 // Work unit: a group of 16 consecutive A sources in (zone, RA-bin) order, one
-// source per lane of a 16-lane DPP row; a wave holds four groups. Each group
-// scans at most MAXR contiguous ranges of the sorted B arrays (its Dec zone,
-// RA window split at the seam, whole ring near a pole). Sixteen B records at a
-// time are loaded, one per lane, and broadcast across the row with DPP
-// row_newbcast, so every lane compares its A with every B without LDS traffic.
+// source per lane of a 16-lane DPP row; a wave holds four groups. A group's
+// B work is the concatenation of at most MAXR ranges of the sorted B records
+// (its Dec zone, RA window split at the seam, whole ring near a pole), taken
+// sixteen at a time: lane l of the row loads item 16c + l of the
+// concatenation, the next chunk's load is issued before the current chunk is
+// tested, and DPP row_newbcast hands each of the sixteen B records to every
+// lane of the row, so every A meets every B without LDS traffic.
+//
+// A lane collects the outcomes of its sixteen tests in a bit mask; the set
+// bits (rare: about one hit per A) are drained into a small per-wave LDS
+// queue, which is appended to the wave's candidate region with one atomic.
+// A second kernel certifies the candidates with all lanes busy, so the
+// filter loop keeps the register budget of a high-occupancy kernel. The paper
+// writes a dense "1" matrix per calculation block (section 4.3.2); here only
+// candidates are stored and only pairs are written.
 //
 // Filters (both end in the same exact decision):
 //   FP64: chord^2 = |u_a - u_b|^2 of FP64 unit vectors. Candidates are pairs
 //     with chord^2 <= t_hi64; below t_lo64 the pair is certainly in and its
 //     separation is 2 asin(chord/2). Between the two it goes to the band list.
-//   FP32: offsets from FP32 cell centres, moved to the frame of the group's
-//     first cell (centre differences are exact in FP32), compared against a
-//     per-group bound that covers the FP32 rounding; every candidate is then
-//     certified with the FP64 haversine of its (ra, dec), and only those within
-//     the FP64 band of r go to the band list.
-// The paper writes a dense "1" matrix per calculation block (section 4.3.2);
-// here hits are compacted per wave (ballot + mbcnt rank) into an LDS queue,
-// certified with all 64 lanes busy, and written with one atomic per wave.
+//   FP32: the same test on FP32 unit vectors against a widened bound that
+//     covers their rounding; every candidate is then certified with the FP64
+//     haversine of its (ra, dec), and only those within the FP64 band of r go
+//     to the band list.
 //
 // FP64 chord error budget (u = 2^-53): each unit-vector component is a
 // product of two degree-reduced sin/cos values (each within ~1.5 ulp) and has
@@ -27,11 +33,16 @@
 // |chord_fp64 - chord| <= sqrt(3)*8u + u*chord ~= 1.6e-15. ETA64 = 4e-15 is
 // used for the thresholds (2.5x margin for the device libm).
 //
-// FP32 filter budget (v = 2^-24): with E >= |u - c0| for every source of the
-// group's window, a shifted offset errs by <= 2vE per component, a difference
-// by <= 4vE + v|d|, so chord_fp32 <= chord(1 + v) + sqrt(3)*4vE and the group
-// threshold (c_r(1+4v) + 8vE)^2 (1+4v) never rejects a true pair.
+// FP32 filter budget (v = 2^-24): a component rounded to FP32 errs by
+// w <= v + 5u from the exact one; the FP32 difference of two components errs
+// by <= 2w + v|d|, so the FP32 chord is <= (chord + 2 sqrt(3) w)(1 + v), and
+// the two fmas and the product add (1 + v)^3 to its square. The bound
+// (c_r (1 + 8u) + 3.5 (v + 5u))^2 (1 + 6v), rounded up to FP32, therefore
+// never rejects a true pair; at r = 2 arcsec it admits chords up to about
+// 2.04 arcsec.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "hlc_kernels.hpp"
 
@@ -39,9 +50,10 @@ namespace hlc {
 
 namespace {
 
-constexpr int MT = 256;                 // threads per block
+constexpr int MT = 256;     // threads per block
 constexpr int WAVES = MT / 64;
-constexpr int QCAP = 64 * (GROUP + 1);  // per-wave queue (flushed after each 16-step batch)
+constexpr int QCAP = 256;   // per-wave candidate queue, staged above QCAP - 64
+constexpr unsigned long long CAND_BLOCKS_MAX = 65536;  // grid cap of the certification walk
 
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
   // consecutive logical blocks on the same XCD (dispatch is round-robin over 8)
@@ -88,100 +100,180 @@ __device__ inline void emit_band(bool band, uint32_t ia, uint32_t ib, const OutA
 }
 
 // ---------------------------------------------------------------------------
-// FP64 form
+// certification of one candidate (A position, B position)
 // ---------------------------------------------------------------------------
-__device__ inline void flush64(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn) {
-  const uint32_t lane = lane_id();
-  count_candidates(qn, o);
-  for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
-    const uint32_t e = b0 + lane;
-    bool in = false, band = false;
-    uint32_t ia = 0, ib = 0;
-    double sep = 0.0;
-    if (e < qn) {
-      uint2 ent = q[e];
-      Rec64 A = a.recA64[ent.x];
-      Rec64 B = a.recB64[ent.y];
-      double dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-      double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      ia = A.idx & IDX_MASK;
-      ib = B.idx & IDX_MASK;
-      // a group straddling two zones also scans the other zone, whose B
-      // entries include halo copies of B sources this A meets in its own
-      // zone: only entries of the A source's own zone count
-      const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-      bool keep = same_zone && (!a.self_only || ia < ib);
-      if (keep && a.hp_order >= 0) {
-        // paper-scheme emulation: count the pair in the smallest shared pixel
-        uint32_t pa[5], pb[5];
-        const double2 ca = a.radecA[ent.x], cb = a.radecB[ent.y];
-        const int na_ = hp_quad(a.hp_order, ca.x, ca.y, a.hp_R, pa);
-        const int nb_ = hp_quad(a.hp_order, cb.x, cb.y, a.hp_R, pb);
-        uint32_t first = 0xffffffffu;
-        for (int u = 0; u < na_; ++u)
-          for (int v = 0; v < nb_; ++v)
-            if (pa[u] == pb[v] && pa[u] < first) first = pa[u];
-        keep = first == a.keysA[ent.x];
-      }
-      double tlo = a.t_lo64, thi = a.t_hi64;
-      if (a.a_err) pair_chord_thr(pair_radius(a, ia, ib), tlo, thi);
-      in = keep && d2 <= tlo;
-      band = keep && !in && d2 <= thi;
-      if (in) sep = 2.0 * asin(0.5 * sqrt(d2)) * RAD2ARCSEC;
-    }
-    emit_wave(in, ia, ib, sep, o);
-    emit_band(band, ia, ib, o);
-  }
-}
-
-template <int N>
-__device__ inline void step64(double ax, double ay, double az, bool a_ok, const double3& b,
-                              double thr, uint32_t a_pos, uint32_t b_pos0, uint2* q, uint32_t& qn) {
-  const double bx = row_bcast<N>(b.x), by = row_bcast<N>(b.y), bz = row_bcast<N>(b.z);
-  const double dx = ax - bx, dy = ay - by, dz = az - bz;
-  const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const bool hit = a_ok && d2 <= thr;
-  const uint64_t m = __ballot(hit);
-  if (m) {
-    if (hit) q[qn + rank_in(m)] = make_uint2(a_pos, b_pos0 + N);
-    qn += (uint32_t)__popcll(m);
-  }
-}
-
-template <int N>
-__device__ inline void steps64(double ax, double ay, double az, bool a_ok, const double3& b,
-                               double thr, uint32_t a_pos, uint32_t b_pos0, uint2* q, uint32_t& qn) {
-  step64<N>(ax, ay, az, a_ok, b, thr, a_pos, b_pos0, q, qn);
-  if constexpr (N + 1 < GROUP) steps64<N + 1>(ax, ay, az, a_ok, b, thr, a_pos, b_pos0, q, qn);
-}
-
-// Per-row cursor over up to MAXR ranges (read from global memory: the
-// range table is indexed dynamically and must not live in registers).
-struct Cursor {
-  uint32_t ri, pos, end;
-  bool active;
+struct Verdict {
+  bool in, band;
+  uint32_t ia, ib;
+  double sep;
 };
 
-__device__ inline void cursor_seek(Cursor& c, const GroupRanges* R) {
-  c.active = false;
-  if (R == nullptr) return;
+template <bool HP>
+__device__ inline Verdict certify64(const MatchArgs& a, uint2 ent) {
+  Verdict v{false, false, 0u, 0u, 0.0};
+  const Rec64 A = a.recA64[ent.x];
+  const Rec64 B = a.recB64[ent.y];
+  const double dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+  const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  v.ia = A.idx & IDX_MASK;
+  v.ib = B.idx & IDX_MASK;
+  // a group straddling two zones (pixels) also scans the other one, whose B
+  // entries include copies of B sources this A meets in its own zone
+  // (pixel): only entries of the A entry's own zone (pixel) count
+  bool keep = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
+  if constexpr (HP) {
+    // paper-scheme emulation: count the pair in the smallest shared pixel
+    uint32_t pa[5], pb[5];
+    const double2 ca = a.radecA[ent.x], cb = a.radecB[ent.y];
+    const int na_ = hp_quad(a.hp_order, ca.x, ca.y, a.hp_R, pa);
+    const int nb_ = hp_quad(a.hp_order, cb.x, cb.y, a.hp_R, pb);
+    uint32_t first = 0xffffffffu;
+    for (int u = 0; u < na_; ++u)
+      for (int w = 0; w < nb_; ++w)
+        if (pa[u] == pb[w] && pa[u] < first) first = pa[u];
+    keep = keep && first == a.keysA[ent.x];
+  }
+  keep = keep && (!a.self_only || v.ia < v.ib);
+  double tlo = a.t_lo64, thi = a.t_hi64;
+  if (a.a_err) pair_chord_thr(pair_radius(a, v.ia, v.ib), tlo, thi);
+  v.in = keep && d2 <= tlo;
+  v.band = keep && !v.in && d2 <= thi;
+  if (v.in) v.sep = 2.0 * asin(0.5 * sqrt(d2)) * RAD2ARCSEC;
+  return v;
+}
+
+__device__ inline Verdict certify32(const MatchArgs& a, uint2 ent) {
+  Verdict v{false, false, 0u, 0u, 0.0};
+  const double2 pa = a.radecA[ent.x];
+  const double2 pb = a.radecB[ent.y];
+  v.ia = a.recA32[ent.x].idx & IDX_MASK;
+  v.ib = a.recB32[ent.y].idx & IDX_MASK;
+  const double h = haversine64(pa.x, pa.y, pb.x, pb.y);
+  const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
+  const bool keep = same_zone && (!a.self_only || v.ia < v.ib);
+  double Hlo = a.H_lo, Hhi = a.H_hi;
+  if (a.a_err) pair_hav_thr(pair_radius(a, v.ia, v.ib), Hlo, Hhi);
+  v.in = keep && h < Hlo;
+  v.band = keep && !v.in && h <= Hhi;
+  if (v.in) v.sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
+  return v;
+}
+
+// Every staged candidate, regions in order: block-wide prefix of the region
+// fills in LDS, then a grid-stride walk over the concatenation.
+template <bool F32, bool HP>
+__global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
+  __shared__ unsigned long long s_pre[NREG + 1];
+  const uint32_t t = threadIdx.x;
+  if (t < NREG) {
+    const unsigned long long f = o.reg.cfill[t * REG_STRIDE];
+    s_pre[t + 1] = f < o.reg.Sc ? f : o.reg.Sc;
+  }
+  if (t == 0) s_pre[0] = 0ull;
+  __syncthreads();
+  // inclusive scan of s_pre[1..NREG] (Hillis-Steele; NREG = blockDim.x)
+  for (uint32_t d = 1; d < NREG; d <<= 1) {
+    unsigned long long x = 0ull;
+    if (t < NREG && t >= d) x = s_pre[t + 1 - d];
+    __syncthreads();
+    if (t < NREG) s_pre[t + 1] += x;
+    __syncthreads();
+  }
+  const unsigned long long total = s_pre[NREG];
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  // uniform trip count so every lane of a wave takes part in the ballots
+  for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const unsigned long long i = base + t;
+    Verdict v{false, false, 0u, 0u, 0.0};
+    if (i < total) {
+      uint32_t lo = 0, hi = NREG;  // region k with s_pre[k] <= i < s_pre[k + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= i) lo = mid; else hi = mid;
+      }
+      const uint2 ent = o.reg.cand[(unsigned long long)lo * o.reg.Sc + (i - s_pre[lo])];
+      if constexpr (F32) v = certify32(a, ent);
+      else v = certify64<HP>(a, ent);
+    }
+    emit_wave(v.in, v.ia, v.ib, v.sep, o);
+    emit_band(v.band, v.ia, v.ib, o);
+  }
+}
+
+// A wave's queue appended to its candidate region (one atomic).
+__device__ inline void stage_candidates(const OutArgs& o, const uint2* q, uint32_t qn) {
+  const uint32_t k = wave_region();
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(&o.reg.cfill[k * REG_STRIDE], (unsigned long long)qn);
+  base = __shfl(base, 0);
+  for (uint32_t e = lane_id(); e < qn; e += 64) {
+    const unsigned long long slot = base + e;
+    if (slot < o.reg.Sc) o.reg.cand[(unsigned long long)k * o.reg.Sc + slot] = q[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the filter
+// ---------------------------------------------------------------------------
+// A group's ranges as one concatenated sequence of B positions.
+struct Flat {
+  uint32_t s0, s1, s2, s3;  // range starts
+  uint32_t p1, p2, p3;      // running lengths after ranges 0, 1, 2
+  uint32_t total;
+};
+
+__device__ inline Flat flatten(const GroupRanges* R) {
+  Flat f{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  if (R == nullptr) return f;
   const uint32_t n = R->count;
-  while (c.ri < n) {
-    c.pos = R->start[c.ri];
-    c.end = R->end[c.ri];
-    if (c.pos < c.end) { c.active = true; return; }
-    ++c.ri;
+  auto len = [&](int t) { return (uint32_t)t < n && R->end[t] > R->start[t] ? R->end[t] - R->start[t] : 0u; };
+  f.s0 = R->start[0];
+  f.s1 = R->start[1];
+  f.s2 = R->start[2];
+  f.s3 = R->start[3];
+  f.p1 = len(0);
+  f.p2 = f.p1 + len(1);
+  f.p3 = f.p2 + len(2);
+  f.total = f.p3 + len(3);
+  return f;
+}
+
+__device__ inline uint32_t flat_pos(const Flat& f, uint32_t t) {
+  return t < f.p1 ? f.s0 + t : t < f.p2 ? f.s1 + (t - f.p1) : t < f.p3 ? f.s2 + (t - f.p2) : f.s3 + (t - f.p3);
+}
+
+template <typename V>
+struct Vec3 {
+  V x, y, z;
+};
+
+template <bool F32>
+__device__ inline Vec3<typename std::conditional<F32, float, double>::type> load_rec(const MatchArgs& a, bool B,
+                                                                                    uint32_t p) {
+  if constexpr (F32) {
+    const Rec32 r = B ? a.recB32[p] : a.recA32[p];
+    return {r.x, r.y, r.z};
+  } else {
+    const Rec64 r = B ? a.recB64[p] : a.recA64[p];
+    return {r.x, r.y, r.z};
   }
 }
 
-__device__ inline void cursor_advance(Cursor& c, const GroupRanges* R) {
-  c.pos += GROUP;
-  if (c.pos < c.end) return;
-  ++c.ri;
-  cursor_seek(c, R);
+// sixteen tests: bit N of mask <- |a - b_N|^2 <= thr, b_N the record of lane
+// N of this lane's row
+template <int N, typename V>
+__device__ inline void tests(const Vec3<V>& A, const Vec3<V>& B, V thr, uint32_t& mask) {
+  const V dx = A.x - row_bcast<N>(B.x);
+  const V dy = A.y - row_bcast<N>(B.y);
+  const V dz = A.z - row_bcast<N>(B.z);
+  const V d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  mask |= (d2 <= thr ? 1u : 0u) << N;
+  if constexpr (N + 1 < GROUP) tests<N + 1, V>(A, B, thr, mask);
 }
 
-__global__ __launch_bounds__(MT) void k_match64(MatchArgs a, OutArgs o) {
+template <bool F32>
+__global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
+  using V = typename std::conditional<F32, float, double>::type;
   __shared__ uint2 s_q[WAVES][QCAP];
   const uint32_t lane = lane_id();
   const uint32_t w = threadIdx.x >> 6;
@@ -194,142 +286,55 @@ __global__ __launch_bounds__(MT) void k_match64(MatchArgs a, OutArgs o) {
   const uint32_t na = a.na.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   const bool grp_ok = grp < ngroups;
-  const GroupRanges* R = grp_ok ? a.ranges + grp : nullptr;
+  const Flat f = flatten(grp_ok ? a.ranges + grp : nullptr);
   const uint32_t a_pos = grp * GROUP + l16;
   bool a_ok = grp_ok && a_pos < na;
-  double ax = 0.0, ay = 0.0, az = 0.0;
+  const V far = (V)1e30;
+  Vec3<V> A{far, far, far};
   if (a_ok) {
-    Rec64 A = a.recA64[a_pos];
-    ax = A.x; ay = A.y; az = A.z;
-    if (a.skip_halo_a && (A.idx & HALO_BIT)) a_ok = false;
+    A = load_rec<F32>(a, false, a_pos);
+    const uint32_t idx = F32 ? a.recA32[a_pos].idx : a.recA64[a_pos].idx;
+    if (a.skip_halo_a && (idx & HALO_BIT)) a_ok = false;
   }
-  const double thr = a.t_hi64;
-  Cursor c;
-  c.ri = 0;
-  cursor_seek(c, R);
-  while (__ballot(c.active)) {
-    double3 b = make_double3(1e30, 1e30, 1e30);
-    uint32_t b0 = c.pos;
-    if (c.active && c.pos + l16 < c.end) {
-      Rec64 B = a.recB64[c.pos + l16];
-      b = make_double3(B.x, B.y, B.z);
-    }
-    steps64<0>(ax, ay, az, a_ok && c.active, b, thr, a_pos, b0, q, qn);
-    if (c.active) cursor_advance(c, R);
-    if (qn >= 64) {
-      flush64(a, o, q, qn);
-      qn = 0;
-    }
-  }
-  if (qn) flush64(a, o, q, qn);
-}
+  if (!a_ok) A = Vec3<V>{-far, -far, -far};
+  V thr;
+  if constexpr (F32) thr = a.thr32;
+  else thr = a.t_hi64;
 
-// ---------------------------------------------------------------------------
-// FP32 form
-// ---------------------------------------------------------------------------
-__device__ inline void cell_centre(const MatchArgs& a, uint32_t k, double& cx, double& cy, double& cz) {
-  const Geom& g = a.geom;
-  double2 zc = a.zone_cs[key_zone(g, k)];
-  double2 sc = a.super_cs[key_bin(g, k) >> g.cell_shift];
-  cx = rint(zc.x * sc.x * 1048576.0) * (1.0 / 1048576.0);
-  cy = rint(zc.x * sc.y * 1048576.0) * (1.0 / 1048576.0);
-  cz = rint(zc.y * 1048576.0) * (1.0 / 1048576.0);
-}
+  // chunk c of the row covers items [16c, 16c + 16) of the concatenation
+  const uint32_t nch = (f.total + 15u) >> 4;
+  uint32_t t = l16;
+  uint32_t bp = t < f.total ? flat_pos(f, t) : 0u;
+  Vec3<V> B{far, far, far};
+  if (t < f.total) B = load_rec<F32>(a, true, bp);
+  for (uint32_t c = 0; __ballot(c < nch); ++c) {
+    // next chunk's record in flight while this one is tested
+    const uint32_t tn = t + GROUP;
+    const uint32_t bpn = tn < f.total ? flat_pos(f, tn) : 0u;
+    Vec3<V> Bn{far, far, far};
+    if (tn < f.total) Bn = load_rec<F32>(a, true, bpn);
 
-__device__ inline void flush32(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn) {
-  const uint32_t lane = lane_id();
-  count_candidates(qn, o);
-  for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
-    const uint32_t e = b0 + lane;
-    bool in = false, band = false;
-    uint32_t ia = 0, ib = 0;
-    double sep = 0.0;
-    if (e < qn) {
-      uint2 ent = q[e];
-      double2 pa = a.radecA[ent.x];
-      double2 pb = a.radecB[ent.y];
-      ia = a.recA32[ent.x].idx & IDX_MASK;
-      ib = a.recB32[ent.y].idx & IDX_MASK;
-      double h = haversine64(pa.x, pa.y, pb.x, pb.y);
-      const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-      const bool keep = same_zone && (!a.self_only || ia < ib);
-      double Hlo = a.H_lo, Hhi = a.H_hi;
-      if (a.a_err) pair_hav_thr(pair_radius(a, ia, ib), Hlo, Hhi);
-      in = keep && h < Hlo;
-      band = keep && !in && h <= Hhi;
-      if (in) sep = 2.0 * asin(sqrt(h)) * RAD2ARCSEC;
+    uint32_t mask = 0u;
+    tests<0, V>(A, B, thr, mask);
+    // drain the hits into the queue, lowest bit first
+    while (__ballot(mask != 0u)) {
+      const bool has = mask != 0u;
+      const uint32_t bit = has ? (uint32_t)__builtin_ctz(mask) : 0u;
+      const uint32_t bpos = (uint32_t)__shfl((int)bp, (int)((lane & 48u) | bit));
+      const uint64_t m = __ballot(has);
+      if (has) q[qn + rank_in(m)] = make_uint2(a_pos, bpos);
+      qn += (uint32_t)__popcll(m);
+      mask &= mask - 1u;
+      if (qn > QCAP - 64) {
+        stage_candidates(o, q, qn);
+        qn = 0;
+      }
     }
-    emit_wave(in, ia, ib, sep, o);
-    emit_band(band, ia, ib, o);
+    t = tn;
+    bp = bpn;
+    B = Bn;
   }
-}
-
-template <int N>
-__device__ inline void steps32(float ax, float ay, float az, bool a_ok, const float3& b, float thr,
-                               uint32_t a_pos, uint32_t b_pos0, uint2* q, uint32_t& qn) {
-  const float bx = row_bcast<N>(b.x), by = row_bcast<N>(b.y), bz = row_bcast<N>(b.z);
-  const float dx = ax - bx, dy = ay - by, dz = az - bz;
-  const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  const bool hit = a_ok && d2 <= thr;
-  const uint64_t m = __ballot(hit);
-  if (m) {
-    if (hit) q[qn + rank_in(m)] = make_uint2(a_pos, b_pos0 + N);
-    qn += (uint32_t)__popcll(m);
-  }
-  if constexpr (N + 1 < GROUP) steps32<N + 1>(ax, ay, az, a_ok, b, thr, a_pos, b_pos0, q, qn);
-}
-
-__global__ __launch_bounds__(MT) void k_match32(MatchArgs a, OutArgs o) {
-  __shared__ uint2 s_q[WAVES][QCAP];
-  const uint32_t lane = lane_id();
-  const uint32_t w = threadIdx.x >> 6;
-  const uint32_t row = lane >> 4, l16 = lane & 15u;
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t grp = (blk * WAVES + w) * 4u + row;
-  uint2* q = s_q[w];
-  uint32_t qn = 0;
-
-  const uint32_t na = a.na.get();
-  const uint32_t ngroups = (na + GROUP - 1) / GROUP;
-  const bool grp_ok = grp < ngroups;
-  const GroupRanges* R = grp_ok ? a.ranges + grp : nullptr;
-  const uint32_t a_pos = grp * GROUP + l16;
-  bool a_ok = grp_ok && a_pos < na;
-  // reference cell: the group's first A source
-  double c0x = 0.0, c0y = 0.0, c0z = 0.0;
-  if (grp_ok) cell_centre(a, a.keysA[grp * GROUP], c0x, c0y, c0z);
-  float ax = 0.f, ay = 0.f, az = 0.f;
-  if (a_ok) {
-    Rec32 A = a.recA32[a_pos];
-    double cx, cy, cz;
-    cell_centre(a, a.keysA[a_pos], cx, cy, cz);
-    ax = A.x + (float)(cx - c0x);
-    ay = A.y + (float)(cy - c0y);
-    az = A.z + (float)(cz - c0z);
-    if (a.skip_halo_a && (A.idx & HALO_BIT)) a_ok = false;
-  }
-  const float thr = grp_ok ? R->thr32 : 0.0f;
-  Cursor c;
-  c.ri = 0;
-  cursor_seek(c, R);
-  while (__ballot(c.active)) {
-    float3 b = make_float3(1e30f, 1e30f, 1e30f);
-    uint32_t b0 = c.pos;
-    if (c.active && c.pos + l16 < c.end) {
-      const uint32_t p = c.pos + l16;
-      Rec32 B = a.recB32[p];
-      double cx, cy, cz;
-      cell_centre(a, a.keysB[p], cx, cy, cz);
-      b = make_float3(B.x + (float)(cx - c0x), B.y + (float)(cy - c0y), B.z + (float)(cz - c0z));
-    }
-    steps32<0>(ax, ay, az, a_ok && c.active, b, thr, a_pos, b0, q, qn);
-    if (c.active) cursor_advance(c, R);
-    if (qn >= 64) {
-      flush32(a, o, q, qn);
-      qn = 0;
-    }
-  }
-  if (qn) flush32(a, o, q, qn);
+  if (qn) stage_candidates(o, q, qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,39 +381,45 @@ __global__ void k_regions_reset(Regions reg) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < NREG) {
     reg.fill[i * REG_STRIDE] = 0ull;
-    reg.cand[i * REG_STRIDE] = 0ull;
+    reg.cfill[i * REG_STRIDE] = 0ull;
   }
 }
 
-// Block k packs region k after the regions before it; block 0 also writes
-// the totals. Contents beyond the caller's capacity are dropped (the call
-// then reports the required count).
+// Blocks k * CPB .. k * CPB + CPB - 1 pack region k after the regions
+// before it; block 0 also writes the totals. Contents beyond the caller's
+// capacity are dropped (the call then reports the required count).
+constexpr uint32_t CPB = 16;  // blocks per region
+
 __global__ __launch_bounds__(256) void k_compact(OutArgs o) {
   __shared__ unsigned long long s_off;
-  const uint32_t k = blockIdx.x;
+  const uint32_t k = blockIdx.x / CPB, part = blockIdx.x % CPB;
   if (threadIdx.x < 64) {
-    unsigned long long off = 0, tot = 0, cand = 0, mx = 0;
+    unsigned long long off = 0, tot = 0, cand = 0, mx = 0, cmx = 0;
     for (uint32_t i = threadIdx.x; i < NREG; i += 64) {
       const unsigned long long f = o.reg.fill[i * REG_STRIDE];
+      const unsigned long long c = o.reg.cfill[i * REG_STRIDE];
       const unsigned long long used = f < o.reg.S ? f : o.reg.S;
       if (i < k) off += used;
       tot += f;
-      cand += o.reg.cand[i * REG_STRIDE];
+      cand += c;
       mx = f > mx ? f : mx;
+      cmx = c > cmx ? c : cmx;
     }
     for (int d = 32; d > 0; d >>= 1) {
       off += __shfl_xor(off, d);
       tot += __shfl_xor(tot, d);
       cand += __shfl_xor(cand, d);
-      const unsigned long long om = __shfl_xor(mx, d);
+      const unsigned long long om = __shfl_xor(mx, d), oc = __shfl_xor(cmx, d);
       mx = om > mx ? om : mx;
+      cmx = oc > cmx ? oc : cmx;
     }
     if (threadIdx.x == 0) {
       s_off = off;
-      if (k == 0) {
+      if (blockIdx.x == 0) {
         o.cnt->n_pairs = tot;
         o.cnt->n_cand = cand;
         o.cnt->region_max = mx;
+        o.cnt->cand_max = cmx;
       }
     }
   }
@@ -416,7 +427,8 @@ __global__ __launch_bounds__(256) void k_compact(OutArgs o) {
   const unsigned long long f = o.reg.fill[k * REG_STRIDE];
   const unsigned long long n = f < o.reg.S ? f : o.reg.S;
   const unsigned long long off = s_off;
-  for (unsigned long long j = threadIdx.x; j < n; j += blockDim.x) {
+  for (unsigned long long j = (unsigned long long)part * blockDim.x + threadIdx.x; j < n;
+       j += (unsigned long long)CPB * blockDim.x) {
     const unsigned long long dst = off + j;
     if (dst >= o.cap) break;
     const unsigned long long src = (unsigned long long)k * o.reg.S + j;
@@ -429,20 +441,24 @@ __global__ __launch_bounds__(256) void k_compact(OutArgs o) {
 
 void launch_regions_reset(const OutArgs& o, hipStream_t s) { k_regions_reset<<<1, NREG, 0, s>>>(o.reg); }
 
-void launch_compact(const OutArgs& o, hipStream_t s) { k_compact<<<NREG, 256, 0, s>>>(o); }
+void launch_compact(const OutArgs& o, hipStream_t s) { k_compact<<<NREG * CPB, 256, 0, s>>>(o); }
 
-void launch_match64(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
-  uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
+void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s) {
+  const uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
   if (ngroups == 0) return;
-  uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
-  k_match64<<<blocks, MT, 0, s>>>(a, o);
+  const uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
+  if (fp32) k_filter<true><<<blocks, MT, 0, s>>>(a, o);
+  else k_filter<false><<<blocks, MT, 0, s>>>(a, o);
 }
 
-void launch_match32(const MatchArgs& a, const OutArgs& o, hipStream_t s) {
-  uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
-  if (ngroups == 0) return;
-  uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
-  k_match32<<<blocks, MT, 0, s>>>(a, o);
+void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s) {
+  // one candidate per thread when the staging is full; the walk is
+  // grid-stride beyond that
+  const unsigned long long slots = (unsigned long long)NREG * o.reg.Sc;
+  const uint32_t blocks = (uint32_t)std::min<unsigned long long>(CAND_BLOCKS_MAX, std::max(1ull, (slots + 255) / 256));
+  if (fp32) k_cand<true, false><<<blocks, 256, 0, s>>>(a, o);
+  else if (a.hp_order >= 0) k_cand<false, true><<<blocks, 256, 0, s>>>(a, o);
+  else k_cand<false, false><<<blocks, 256, 0, s>>>(a, o);
 }
 
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,

@@ -26,14 +26,22 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 4096 keys per tile
 constexpr int RS_BINS = 256;
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = RS_THREADS * SCAN_ITEMS;
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// keys and values [0, count) from one buffer pair to another
+__global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ vs,
+                             uint32_t* __restrict__ kd, uint32_t* __restrict__ vd, DevCount nc) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc.get()) {
+    kd[i] = ks[i];
+    vd[i] = vs[i];
+  }
 }
 
 __global__ void k_zero_counters(Counters* c) {
@@ -73,11 +81,25 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uin
 constexpr int KG_ITEMS = 16;
 constexpr uint32_t KG_TILE = KG_ITEMS * 256;
 
+__device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
+  double sd, cd, sa, ca;
+  sincos_deg(dec, &sd, &cd);
+  sincos_deg(ra, &sa, &ca);
+  x = cd * ca;
+  y = cd * sa;
+  z = sd;
+}
+
+// Besides the keys, each source's working record is written in input order
+// (coalesced), so the layout after the sort is a single 32-B gather per
+// entry instead of two 8-B gathers of (ra, dec) that each cost a cache line.
 __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
                                                 uint32_t* __restrict__ keys,
-                                                uint32_t* __restrict__ vals, Counters* cnt) {
+                                                uint32_t* __restrict__ vals, Counters* cnt,
+                                                Rec64* __restrict__ src64,
+                                                SrcRec32* __restrict__ src32) {
   __shared__ uint32_t s_w[4];
   __shared__ unsigned long long s_base;
   const uint32_t t = threadIdx.x;
@@ -101,6 +123,29 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
       const uint32_t b = bin_of(g, a);
       keys[i] = make_key(g, z, b);
       vals[i] = i;
+      if (src64 || src32) {
+        double x, y, w;
+        unit_vector(a, d, x, y, w);
+        if (src64) {
+          Rec64 r;
+          r.x = x;
+          r.y = y;
+          r.z = w;
+          r.idx = i;
+          r.pad = 0u;
+          src64[i] = r;
+        }
+        if (src32) {
+          SrcRec32 r;
+          r.x = (float)x;
+          r.y = (float)y;
+          r.z = (float)w;
+          r.idx = i;
+          r.ra = a;
+          r.dec = d;
+          src32[i] = r;
+        }
+      }
       if (halo && ok) {
         // the zone height is >= 2 r, so the padded Dec window reaches at
         // most one neighbouring zone
@@ -153,58 +198,29 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
   counts[t * ntiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                            uint32_t n, uint32_t* block_sums) {
+// Block d: exclusive scan, in place, of digit d's per-tile counts (tile
+// order); the digit's total goes to totals[d]. The scatter adds the
+// exclusive prefix of the totals, so one launch replaces a device-wide scan.
+__global__ __launch_bounds__(RS_THREADS) void k_scan_digits(uint32_t* __restrict__ counts, uint32_t ntiles,
+                                                            uint32_t* __restrict__ totals) {
   __shared__ uint32_t s_w[4];
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
-    if (base + j < n) s += in[base + j];
-  uint32_t tot;
-  block_exclusive_scan(s, &tot, s_w);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
-}
-
-// Single block: exclusive scan of nb values in place, any nb.
-__global__ __launch_bounds__(RS_THREADS) void k_scan_top(uint32_t* v, uint32_t nb) {
-  __shared__ uint32_t s_w[4];
+  uint32_t* c = counts + (size_t)blockIdx.x * ntiles;
   uint32_t carry = 0;
-  for (uint32_t off = 0; off < nb; off += RS_THREADS) {
-    uint32_t i = off + threadIdx.x;
-    uint32_t x = i < nb ? v[i] : 0u;
+  for (uint32_t off = 0; off < ntiles; off += RS_THREADS) {
+    const uint32_t i = off + threadIdx.x;
+    const uint32_t x = i < ntiles ? c[i] : 0u;
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan(x, &tot, s_w);
-    if (i < nb) v[i] = carry + ex;
+    const uint32_t ex = block_exclusive_scan(x, &tot, s_w);
+    if (i < ntiles) c[i] = carry + ex;
     carry += tot;
   }
-}
-
-__global__ __launch_bounds__(RS_THREADS) void k_scan_down(const uint32_t* in,
-                                                          uint32_t* out, uint32_t n,
-                                                          const uint32_t* __restrict__ block_sums) {
-  __shared__ uint32_t s_w[4];
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t x[SCAN_ITEMS];
-  uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j) {
-    x[j] = (base + j < n) ? in[base + j] : 0u;
-    s += x[j];
-  }
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, &tot, s_w) + block_sums[blockIdx.x];
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j) {
-    if (base + j < n) out[base + j] = run;
-    run += x[j];
-  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, DevCount nc, int shift,
-    const uint32_t* __restrict__ offsets, uint32_t ntiles) {
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ totals, uint32_t ntiles) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[RS_TILE];
   __shared__ uint32_t s_wh[4][RS_BINS];
@@ -219,7 +235,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
 
   for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
-  s_goff[t] = offsets[t * ntiles + tile];
+  {
+    uint32_t all;
+    const uint32_t digit_base = block_exclusive_scan(totals[t], &all, s_w);
+    s_goff[t] = digit_base + offsets[t * ntiles + tile];
+  }
   __syncthreads();
 
   // wave w owns tile elements [w*1024, (w+1)*1024), 64 per round
@@ -283,8 +303,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 // ---------------------------------------------------------------------------
 // zone / cell tables
 // ---------------------------------------------------------------------------
-__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double2* __restrict__ zone_cs,
-                              double2* __restrict__ super_cs) {
+// RA margin of each zone in bins (-1: the zone is scanned as a whole ring)
+__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (uint32_t)g.nz) {
     const int32_t z = (int32_t)i;
@@ -305,17 +325,7 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double2* __re
         if (2.0 * mm + 1.0 < (double)g.nbins) m = (int32_t)mm;
       }
     }
-    if (zmarg != nullptr) zmarg[z] = m;
-    double mid = fmin(fmax(-90.0 + ((double)z + 0.5) * g.h_deg, -90.0), 90.0);
-    double s, c;
-    sincos_deg(mid, &s, &c);
-    zone_cs[z] = make_double2(c, s);
-  }
-  if (super_cs != nullptr && i < g.nsuper) {
-    double mid = ((double)i + 0.5) * (360.0 / (double)g.nsuper);
-    double s, c;
-    sincos_deg(mid, &s, &c);
-    super_cs[i] = make_double2(c, s);
+    zmarg[z] = m;
   }
 }
 
@@ -340,15 +350,6 @@ __global__ void k_zone_starts(const uint32_t* __restrict__ keys, DevCount nc, Ge
 // ---------------------------------------------------------------------------
 // working layouts
 // ---------------------------------------------------------------------------
-__device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
-  double sd, cd, sa, ca;
-  sincos_deg(dec, &sd, &cd);
-  sincos_deg(ra, &sa, &ca);
-  x = cd * ca;
-  y = cd * sa;
-  z = sd;
-}
-
 __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
@@ -368,25 +369,11 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
   rec[p] = r;
 }
 
-__device__ inline double snap20(double v) { return rint(v * 1048576.0) * (1.0 / 1048576.0); }
-
-// Centre of the FP32 cell holding key k, snapped to a 2^-20 grid so that
-// differences of two centres are exact in FP32.
-__device__ inline void cell_centre(const Geom& g, const double2* zone_cs, const double2* super_cs,
-                                   uint32_t k, double& cx, double& cy, double& cz) {
-  double2 zc = zone_cs[key_zone(g, k)];
-  double2 sc = super_cs[key_bin(g, k) >> g.cell_shift];
-  cx = snap20(zc.x * sc.x);
-  cy = snap20(zc.x * sc.y);
-  cz = snap20(zc.y);
-}
-
-__global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ keys,
-                                                  const uint32_t* __restrict__ vals, DevCount nc,
+// FP32 unit vector (each component rounded once from FP64) and the FP64
+// (ra, dec) that certifies its candidates
+__global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
-                                                  const double* __restrict__ dec, Geom g,
-                                                  const double2* __restrict__ zone_cs,
-                                                  const double2* __restrict__ super_cs,
+                                                  const double* __restrict__ dec,
                                                   Rec32* __restrict__ rec,
                                                   double2* __restrict__ radec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -394,16 +381,44 @@ __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ k
   uint32_t v = vals[p];
   uint32_t i = v & IDX_MASK;
   double a = ra[i], d = dec[i];
-  double x, y, z, cx, cy, cz;
+  double x, y, z;
   unit_vector(a, d, x, y, z);
-  cell_centre(g, zone_cs, super_cs, keys[p], cx, cy, cz);
   Rec32 r;
-  r.x = (float)(x - cx);
-  r.y = (float)(y - cy);
-  r.z = (float)(z - cz);
+  r.x = (float)x;
+  r.y = (float)y;
+  r.z = (float)z;
   r.idx = v;
   rec[p] = r;
   radec[p] = make_double2(a, d);
+}
+
+// Sorted working records from the per-source records of the keygen.
+__global__ __launch_bounds__(256) void k_gather64(const uint32_t* __restrict__ vals, DevCount nc,
+                                                  const Rec64* __restrict__ src,
+                                                  Rec64* __restrict__ rec) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc.get()) return;
+  const uint32_t v = vals[p];
+  Rec64 r = src[v & IDX_MASK];
+  r.idx = v;
+  rec[p] = r;
+}
+
+__global__ __launch_bounds__(256) void k_gather32(const uint32_t* __restrict__ vals, DevCount nc,
+                                                  const SrcRec32* __restrict__ src,
+                                                  Rec32* __restrict__ rec,
+                                                  double2* __restrict__ radec) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc.get()) return;
+  const uint32_t v = vals[p];
+  const SrcRec32 r = src[v & IDX_MASK];
+  Rec32 o;
+  o.x = r.x;
+  o.y = r.y;
+  o.z = r.z;
+  o.idx = v;
+  rec[p] = o;
+  radec[p] = make_double2(r.ra, r.dec);
 }
 
 // ---------------------------------------------------------------------------
@@ -524,7 +539,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
                                                 const uint32_t* __restrict__ keysB,
                                                 const uint32_t* __restrict__ zstartB,
                                                 const int32_t* __restrict__ zmarg, Geom g,
-                                                double c_r, GroupRanges* __restrict__ out) {
+                                                GroupRanges* __restrict__ out) {
   const uint32_t na = nac.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,8 +551,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
   RangeList L;
   L.n = 0;
   const int64_t nbins = g.nbins;
-  bool full_any = false;
-  int64_t ra_lo = INT64_MAX, ra_hi = INT64_MIN;  // unwrapped bin extent of all windows
   uint32_t q = 0;
   while (q < cnt) {
     const int32_t z = key_zone(g, k[q]);
@@ -548,7 +561,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     const int32_t m = zmarg[z];
     const int64_t lo = bf - m, hi = bl + m;
     if (m < 0 || hi - lo + 1 >= nbins) {
-      full_any = true;
       L.add(zs, ze);
     } else if (zs < ze) {
       uint32_t s = gallop_lower(keysB, make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)), lb[p0 + q], zs, ze);
@@ -564,8 +576,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
         L.add(s2, ze);
       }
     }
-    if (lo < ra_lo) ra_lo = lo;
-    if (hi > ra_hi) ra_hi = hi;
     q = qe + 1;
   }
   // keep at most MAXR ranges by merging across the smallest gaps
@@ -589,21 +599,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     R.end[t] = t < L.n ? L.e[t] : 0u;
   }
   R.count = (uint32_t)L.n;
-  // FP32 acceptance threshold: bound E on |u - c0| over the group's window
-  // (Dec span + RA span + two cell diagonals, as arcs >= chords), then
-  // chord_fp32 <= chord + 8 * 2^-24 * E (see the error budget in match.hip).
-  const int32_t z0 = key_zone(g, k[0]), z1 = key_zone(g, k[cnt - 1]);
-  double span_dec = (double)(z1 - z0 + 1) * g.h_deg + 2.0 * g.rpad_deg;
-  double span_ra = full_any ? 360.0 : fmin(360.0, (double)(ra_hi - ra_lo + 1) / g.bin_scale);
-  double cell = g.h_deg + 360.0 / (double)g.nsuper;
-  double E = fmin(2.0, (span_dec + span_ra + 2.0 * cell) * (M_PI / 180.0));
-  const double u32 = 5.9604644775390625e-08;  // 2^-24
-  double c = c_r * (1.0 + 4.0 * u32) + 8.0 * u32 * E;
-  double T = c * c * (1.0 + 4.0 * u32);
-  float Tf = (float)T;
-  if ((double)Tf < T) Tf = __uint_as_float(__float_as_uint(Tf) + 1u);  // round up (Tf > 0)
-  R.thr32 = Tf;
-  R.pad_[0] = R.pad_[1] = 0u;
+  R.pad_[0] = R.pad_[1] = R.pad_[2] = 0u;
   out[grp] = R;
 }
 
@@ -710,9 +706,37 @@ __global__ __launch_bounds__(256) void k_equal_ranges(const uint32_t* __restrict
     R.end[t] = t < L.n ? L.e[t] : 0u;
   }
   R.count = (uint32_t)L.n;
-  R.thr32 = 0.0f;
-  R.pad_[0] = R.pad_[1] = 0u;
+  R.pad_[0] = R.pad_[1] = R.pad_[2] = 0u;
   out[grp] = R;
+}
+
+// ---------------------------------------------------------------------------
+// ordering of an output pair list by (a, b)
+// ---------------------------------------------------------------------------
+__global__ void k_pairs_keys(const uint2* __restrict__ p, uint32_t n, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    keys[i] = p[i].y;
+    vals[i] = i;
+  }
+}
+
+__global__ void k_pairs_rekey(const uint2* __restrict__ p, const uint32_t* __restrict__ vals, uint32_t n,
+                              uint32_t* __restrict__ keys) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = p[vals[i]].x;
+}
+
+__global__ void k_pairs_permute(const uint2* __restrict__ p, const double* __restrict__ sep,
+                                const uint32_t* __restrict__ vals, uint32_t n, uint2* __restrict__ tp,
+                                double* __restrict__ ts) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint32_t j = vals[i];
+    tp[i] = p[j];
+    if (sep) ts[i] = sep[j];
+  }
 }
 
 }  // namespace
@@ -754,43 +778,69 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64, 0, s>>>(c); }
 
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
-                   uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s) {
+                   uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
+                   Rec64* src64, SrcRec32* src32) {
   if (n == 0) return;
-  k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt);
+  k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys,
+                                                                    vals, cnt, src64, src32);
+}
+
+void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s) {
+  if (n.cap == 0) return;
+  k_gather64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
+}
+
+void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* src, Rec32* rec, double2* radec,
+                     hipStream_t s) {
+  if (n.cap == 0) return;
+  k_gather32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec, radec);
 }
 
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
-size_t sort_block_sums_len(uint32_t n) { return std::max<size_t>(1, cdiv(sort_counts_len(n), SCAN_TILE)); }
+size_t sort_digit_totals_len(uint32_t n) { (void)n; return RS_BINS; }
+
+int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
 
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
-                hipStream_t s) {
+                hipStream_t s, bool from_alt) {
   const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
-  if (n <= 1) return;
-  const uint32_t ntiles = cdiv(n, RS_TILE);
-  const uint32_t nc = RS_BINS * ntiles;
-  const uint32_t nsb = cdiv(nc, SCAN_TILE);
+  const int passes = radix_passes(key_bits);
   uint32_t *kin = keys, *vin = vals, *kout = sc.keys_alt, *vout = sc.vals_alt;
-  int passes = (key_bits + 7) / 8;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles);
-    k_scan_reduce<<<nsb, RS_THREADS, 0, s>>>(sc.counts, nc, sc.block_sums);
-    k_scan_top<<<1, RS_THREADS, 0, s>>>(sc.block_sums, nsb);
-    k_scan_down<<<nsb, RS_THREADS, 0, s>>>(sc.counts, sc.counts, nc, sc.block_sums);
-    k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts, ntiles);
+  if (from_alt) {
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  if (kin != keys) {
-    (void)hipMemcpyAsync(keys, kin, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-    (void)hipMemcpyAsync(vals, vin, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+  if (n > 1) {
+    const uint32_t ntiles = cdiv(n, RS_TILE);
+    for (int p = 0; p < passes; ++p) {
+      const int shift = 8 * p;
+      k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles);
+      k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
+      k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts,
+                                                    sc.digit_totals, ntiles);
+      std::swap(kin, kout);
+      std::swap(vin, vout);
+    }
   }
+  if (kin != keys && n > 0) k_copy_pairs<<<cdiv(n, 256), 256, 0, s>>>(kin, vin, keys, vals, cnt);
 }
 
-void launch_zone_tables(const Geom& g, int32_t* zmarg, double2* zone_cs, double2* super_cs,
-                        hipStream_t s) {
-  uint32_t n = std::max<uint32_t>((uint32_t)g.nz, super_cs ? g.nsuper : 0u);
-  k_zone_tables<<<cdiv(n, 256), 256, 0, s>>>(g, zmarg, zone_cs, super_cs);
+void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, uint32_t* keys, uint32_t* vals,
+                uint2* tmp_pairs, double* tmp_sep, const SortScratch& sc, hipStream_t s) {
+  if (n <= 1) return;
+  const DevCount cnt{n, n, nullptr};
+  // stable by b, then stable by a: (a, b) order
+  k_pairs_keys<<<cdiv(n, 256), 256, 0, s>>>(pairs, n, keys, vals);
+  radix_sort(keys, vals, cnt, bits_b, sc, s);
+  k_pairs_rekey<<<cdiv(n, 256), 256, 0, s>>>(pairs, vals, n, keys);
+  radix_sort(keys, vals, cnt, bits_a, sc, s);
+  k_pairs_permute<<<cdiv(n, 256), 256, 0, s>>>(pairs, sep, vals, n, tmp_pairs, tmp_sep);
+  (void)hipMemcpyAsync(pairs, tmp_pairs, (size_t)n * sizeof(uint2), hipMemcpyDeviceToDevice, s);
+  if (sep) (void)hipMemcpyAsync(sep, tmp_sep, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+void launch_zone_tables(const Geom& g, int32_t* zmarg, hipStream_t s) {
+  k_zone_tables<<<cdiv((uint32_t)g.nz, 256), 256, 0, s>>>(g, zmarg);
 }
 
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
@@ -804,11 +854,10 @@ void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, 
   k_layout64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
 }
 
-void launch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,
-                     const double* dec, const Geom& g, const double2* zone_cs,
-                     const double2* super_cs, Rec32* rec, double2* radec, hipStream_t s) {
+void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
+                     Rec32* rec, double2* radec, hipStream_t s) {
   if (n.cap == 0) return;
-  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(keys, vals, n, ra, dec, g, zone_cs, super_cs, rec, radec);
+  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec, radec);
 }
 
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
@@ -819,11 +868,11 @@ void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* 
 }
 
 void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
-                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g, double c_r,
+                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
                    GroupRanges* out, hipStream_t s) {
   uint32_t ngroups = cdiv(na.cap, GROUP);
   if (ngroups == 0) return;
-  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, zstartB, zmarg, g, c_r, out);
+  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, zstartB, zmarg, g, out);
 }
 
 }  // namespace hlc

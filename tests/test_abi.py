@@ -80,9 +80,10 @@ def test_argument_errors_are_caught_before_any_device_call(lib):
     assert lib.hlc_xmatch(fake, fake, 1, fake, fake, 1, 1.0, fake, None, C.byref(o)) == hlc.HLC_E_INVAL
     # missing coordinates with n > 0
     assert lib.hlc_xmatch(None, fake, 1, fake, fake, 1, 1.0, fake, fake, C.byref(o)) == hlc.HLC_E_INVAL
-    # sorted output is not provided
+    # a sorted order cannot be given for pairs that are handed over per chunk
     o.flags = hlc.HLC_SORTED
-    assert lib.hlc_xmatch(fake, fake, 1, fake, fake, 1, 1.0, fake, fake, C.byref(o)) == hlc.HLC_E_UNSUPPORTED
+    sink = hlc.SINK(lambda p, s_, n, u: 0)
+    assert lib.hlc_xmatch_stream(fake, fake, 1, fake, fake, 1, 1.0, sink, None, C.byref(o)) == hlc.HLC_E_UNSUPPORTED
     assert lib.hlc_last_stats(None) == hlc.HLC_E_INVAL
 
 

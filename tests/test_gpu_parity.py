@@ -56,18 +56,18 @@ def test_adversarial(hlc, kind, prec):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
-def test_zone_heights_and_cells(hlc, prec):
-    """Tuned geometries: thin zones (many halo copies), wide zones, coarse and fine cells."""
+def test_zone_heights_and_bins(hlc, prec):
+    """Tuned geometries: thin zones (many halo copies), wide zones, coarse and fine RA bins."""
     a_ra, a_dec, b_ra, b_dec = synth.adversarial("dense", 3001, 5, 2.0)
     pr, pd = synth.polar_caps(synth.rng(77, 0), 3000, 0.05)
     a_ra, a_dec = np.concatenate([a_ra, pr[:1500]]), np.concatenate([a_dec, pd[:1500]])
     b_ra, b_dec = np.concatenate([b_ra, pr[1500:]]), np.concatenate([b_dec, pd[1500:]])
     ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, 2.0)
     for zh in (4.01, 5.0, 30.0, 700.0, 3600.0 * 4):
-        for cells in (0, 1, 6, 14):
-            tun = {"zone_height_arcsec": zh, "ra_cell_bins_log2": cells}
+        for bins in (0, 1, 6, 14, 30):
+            tun = {"zone_height_arcsec": zh, "ra_bins_log2": bins}
             keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec, tuning=tun)
-            assert_same(keys, sep, ref, label=f"zh={zh} cells={cells}")
+            assert_same(keys, sep, ref, label=f"zh={zh} bins={bins}")
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
@@ -330,3 +330,48 @@ def test_error_radii(hlc, prec):
     st, _ = hlc.hlc_xmatch_radii(to_dev(A_ra), to_dev(A_dec), to_dev(ea), to_dev(A_ra), to_dev(B_dec),
                                  to_dev(bad), 3.0, out, sep, precision=prec)
     assert st == hlc.HLC_E_INVAL
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_sorted_output(hlc, prec):
+    """HLC_SORTED: the pair list comes back in (a, b) order, element by element equal to the
+    oracle's sorted list; also for a self-match, a partition pair and the batched form."""
+    import torch
+    c = synth.patch_pair(scale=0.2)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)  # sorted by (a, b)
+    rk = ref.keys()
+    cap = len(rk) + 100
+    args = [to_dev(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+
+    def check(out, sep, n, rk, rs, label):
+        p = out[:n].cpu().numpy().view(np.uint32).reshape(-1, 2)
+        k = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+        assert np.array_equal(k, rk), label
+        assert np.max(np.abs(sep[:n].cpu().numpy() - rs)) <= 1e-9, label
+
+    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    sep = torch.empty(cap, dtype=torch.float64, device="cuda")
+    st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, sep, precision=prec, flags=hlc.HLC_SORTED)
+    assert st == hlc.HLC_OK
+    check(out, sep, n, rk, ref.sep, "xmatch")
+
+    A = hlc.hlc_partition(args[0], args[1], c.r_arcsec)
+    B = hlc.hlc_partition(args[2], args[3], c.r_arcsec)
+    st, n = hlc.hlc_xmatch_part(A, B, c.r_arcsec, out, sep, precision=prec, flags=hlc.HLC_SORTED)
+    assert st == hlc.HLC_OK
+    check(out, sep, n, rk, ref.sep, "part")
+    A.free()
+    B.free()
+
+    jobs = [(0, len(c.a_ra), 0, len(c.b_ra), c.r_arcsec)]
+    st, n = hlc.hlc_xmatch_batch(jobs, *args, out, sep, precision=prec, flags=hlc.HLC_SORTED)
+    assert st == hlc.HLC_OK
+    check(out, sep, n, rk, ref.sep, "batch")
+
+    sref = oracle.xmatch(c.b_ra, c.b_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    keep = sref.a < sref.b
+    sk = sref.keys()[keep]
+    st, n = hlc.hlc_xmatch(args[2], args[3], args[2], args[3], c.r_arcsec, out, sep, precision=prec,
+                           flags=hlc.HLC_SORTED | hlc.HLC_SELF)
+    assert st == hlc.HLC_OK
+    check(out, sep, n, sk, sref.sep[keep], "self")

@@ -355,8 +355,10 @@ def test_sorted_output(hlc, prec):
     assert st == hlc.HLC_OK
     check(out, sep, n, rk, ref.sep, "xmatch")
 
-    A = hlc.hlc_partition(args[0], args[1], c.r_arcsec)
-    B = hlc.hlc_partition(args[2], args[3], c.r_arcsec)
+    st, A = hlc.hlc_partition(args[0], args[1], c.r_arcsec)
+    assert st == hlc.HLC_OK
+    st, B = hlc.hlc_partition(args[2], args[3], c.r_arcsec)
+    assert st == hlc.HLC_OK
     st, n = hlc.hlc_xmatch_part(A, B, c.r_arcsec, out, sep, precision=prec, flags=hlc.HLC_SORTED)
     assert st == hlc.HLC_OK
     check(out, sep, n, rk, ref.sep, "part")

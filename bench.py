@@ -25,17 +25,71 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per launch of the filter kernel (the dominant kernel):
-# the working records of both sides read once, each candidate (A position,
-# B position: 2 x u32) written once.
+# the working records of both sides read once, each staged candidate (A's
+# FP64 data, A index, B position: 32 B) written once.
 #   FP64 form: 32 B per A record, 32 B per B entry (x, y, z f64 + index).
-#   FP32 form: 16 B per A record, 16 B per B entry (x, y, z f32 + index).
+#   FP32 form: 32 B per A record (x, y, z f32 + index + FP64 ra, dec, which
+#              the candidates carry), 16 B per B entry (x, y, z f32 + index).
 MATCH_BYTES = {
-    "fp64": lambda na, nbh, npairs, ncand: 32 * na + 32 * nbh + 8 * ncand,
-    "fp32": lambda na, nbh, npairs, ncand: 16 * na + 16 * nbh + 8 * ncand,
+    "fp64": lambda na, nbh, npairs, ncand: 32 * na + 32 * nbh + 32 * ncand,
+    "fp32": lambda na, nbh, npairs, ncand: 32 * na + 16 * nbh + 32 * ncand,
 }
 # Whole-call canonical bytes: FP64 (ra, dec) of every source read once and
 # every pair written once.
 CALL_BYTES = lambda na, nb, npairs: 16 * (na + nb) + 16 * npairs
+
+# HBM traffic of the filter kernel, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE passes, scaled by a 1 GiB copy) and recorded
+# with a hash of the kernel sources it was measured on; reported only while
+# the sources are unchanged.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_k_filter_fullsky_10Mx10M_r2.md")
+KERNEL_SOURCES = ["match.hip", "hlc_device.hpp", "hlc_kernels.hpp"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_07331_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Bytes per launch from the committed record, or None if the kernel sources changed since."""
+    try:
+        text = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha256")))
+    if fields.get("source_sha256", "").strip() != kernel_sources_sha256():
+        return None
+    return float(fields["traffic_bytes"])
+
+
+def traffic_from_pmc(fetch_dir, write_dir, kernel="k_filter<true>"):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of
+    `bench.py --copy-calibration` (FETCH_SIZE, WRITE_SIZE in KiB per
+    dispatch), each scaled so that the 1 GiB device copy reads / writes 1 GiB."""
+    import csv
+
+    def per_kernel(d, counter):
+        rows = [r for r in csv.DictReader(open(os.path.join(d, "p_counter_collection.csv")))
+                if r["Counter_Name"] == counter]
+        target = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if "hlc" not in r["Kernel_Name"] and ("copy" in r["Kernel_Name"].lower()
+                                                        or "elementwise" in r["Kernel_Name"].lower())]
+        return sum(target) / len(target), max(copies)
+
+    f_k, f_copy = per_kernel(fetch_dir, "FETCH_SIZE")
+    w_k, w_copy = per_kernel(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fetch = f_k * (gib_kib / f_copy) * 1024.0
+    write = w_k * (gib_kib / w_copy) * 1024.0
+    return {"fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
+            "fetch_scale": gib_kib / f_copy, "write_scale": gib_kib / w_copy,
+            "source_sha256": kernel_sources_sha256()}
 
 
 def parse():
@@ -51,7 +105,10 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
     p.add_argument("--forms", default="xmatch,batch,quad",
-                   help="xmatch (the headline, always run), batch (10,000 jobs), quad (paper-scheme emulation)")
+                   help="xmatch (the headline, always run), batch (10,000 jobs), quad (paper-scheme "
+                        "emulation), stream (400M x 100M from pinned host memory; not in the default set)")
+    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="print the filter kernel's HBM traffic from two rocprofv3 --pmc output folders and exit")
     return p.parse_args()
 
 
@@ -114,6 +171,48 @@ def bench_batch(hlc, torch, dev, steps, warmup):
     return res
 
 
+def bench_stream(hlc, torch):
+    """The streaming form on the 400M x 100M workload held in pinned host
+    memory: wall time of one call including every host <-> device copy
+    (PCIe-inclusive), with a sink that only counts the pairs it is handed."""
+    import synth
+    t0 = time.time()
+    c = synth.large_pair()
+    print(f"[bench] generated {c.name} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def pinned(x):
+        t = torch.empty(len(x), dtype=torch.float64, pin_memory=True)
+        t.numpy()[:] = x
+        return t
+
+    arrs = [pinned(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+    na, nb, r, name_w = c.na, c.nb, c.r_arcsec, c.name
+    del c
+    res = {}
+    for name, prec in (("fp32", hlc.HLC_FP32_RECHECK), ("fp64", hlc.HLC_FP64)):
+        got = [0]
+
+        def sink(p, s_, k):
+            got[0] += k
+            return 0
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, n = hlc.hlc_xmatch_stream(*arrs, r, sink, precision=prec, ring_pairs=1 << 26)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        if st != hlc.HLC_OK or got[0] != n:
+            raise hlc.HLCError(st, "stream")
+        h2d = 16 * (na + nb)
+        d2h = 16 * n
+        res[name] = {"seconds": sec, "a_sources_per_s_pcie_inclusive": na / sec, "pairs": int(n),
+                     "h2d_bytes": h2d, "d2h_bytes": d2h, "link_gbs": (h2d + d2h) / sec / 1e9}
+        print(f"[bench] stream {name}: {sec:.2f} s, {n} pairs", file=sys.stderr, flush=True)
+    res["workload"] = f"{name_w}: {na} A x {nb} B in pinned host memory, r={r} arcsec"
+    res["transfer_model"] = hlc.transfer_model()
+    return res
+
+
 def bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, exact_pairs):
     """The paper's HEALPix + quad-direction partition, emulated on the same
     workload: pairs it finds (a subset of the exact set), the loss, and time."""
@@ -136,6 +235,9 @@ def bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, exact_pairs):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        print(json.dumps(traffic_from_pmc(*args.traffic_from)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the cross-match "
               "is built and measured on a single MI355X.", file=sys.stderr)
@@ -219,17 +321,20 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": None,
+        "traffic": recorded_traffic() if head_name == "fp32" else None,
     }
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     extra = {}
     if "quad" in forms:
         extra["quad_direction"] = bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, head["n_pairs"])
-    if "batch" in forms:
+    if "batch" in forms or "stream" in forms:
         del a_ra, a_dec, b_ra, b_dec, out, sep
         torch.cuda.empty_cache()
+    if "batch" in forms:
         extra["batch"] = bench_batch(hlc, torch, dev, args.steps, args.warmup)
+    if "stream" in forms:
+        extra["stream"] = bench_stream(hlc, torch)
 
     cpu = None
     if not args.no_cpu_baseline:

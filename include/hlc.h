@@ -80,7 +80,8 @@ typedef struct {
 typedef struct hlc_tuning {
   double zone_height_arcsec; /* Dec zone height; >= 2.0001 r is enforced       */
   int32_t ra_bins_log2;      /* log2 of RA bins per zone, 1..30 (0 = auto)     */
-  int32_t reserved0;
+  int32_t filter_items;       /* work items (four groups of 16 A) per wave of   *
+                              * the filter kernel (0 = one)                    */
   double zone_height_factor; /* batched form: scale of each job's density-     *
                               * derived zone height (0 = autotuned and cached)  */
   int32_t reserved[4];

@@ -41,6 +41,7 @@ struct Device {
   // staging sizes that earlier calls needed (grow-only), so a repeated
   // workload does not pay the overflow re-run again
   uint64_t hint_stage = 0, hint_cand = 0;
+  int ncu = 0;  // compute units (persistent grids)
 };
 
 Device g_dev[MAX_DEVICES];
@@ -73,6 +74,7 @@ int get_device(Device** out, int* dev_id = nullptr) {
     HLC_TRY(hipMalloc(&d.cnt, sizeof(Counters)));
     HLC_TRY(hipHostMalloc(&d.cnt_host, sizeof(Counters), hipHostMallocDefault));
     for (auto& e : d.ev) HLC_TRY(hipEventCreate(&e));
+    HLC_TRY(hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, dev));
     d.init = true;
   }
   *out = &d;
@@ -222,6 +224,7 @@ double tuned_height(const hlc_opts* o) {
   return (o->tuning && o->tuning->zone_height_arcsec > 0) ? o->tuning->zone_height_arcsec : 0.0;
 }
 int tuned_bins(const hlc_opts* o) { return o->tuning ? o->tuning->ra_bins_log2 : 0; }
+int tuned_items(const hlc_opts* o) { return (o->tuning && o->tuning->filter_items > 0) ? o->tuning->filter_items : 1; }
 
 // One partitioned catalogue.
 struct Side {
@@ -248,6 +251,9 @@ void mark(Device& dev, int slot, hipStream_t s) {
   if (slot >= 0) (void)hipEventRecord(dev.ev[slot], s);
 }
 
+// l64 / l32: the side's records are FP64 / FP32; without a sorted layout
+// (sd.r64 / sd.r32 null) the per-source records stay in input order and the
+// kernels read them through vals
 int partition(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
               bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd,
               const Slots& sl, hipStream_t s) {
@@ -265,11 +271,11 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
   mark(dev, sl.sort_begin, s);
   radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt);
   mark(dev, sl.sort, s);
-  if (l64) {
+  if (l64 && sd.r64) {
     if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
     else launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
   }
-  if (l32) {
+  if (l32 && sd.r32) {
     if (sd.src32) launch_gather32(sd.vals, sd.cnt, sd.src32, sd.r32, sd.radec, s);
     else launch_layout32(sd.vals, sd.cnt, ra, dec, sd.r32, sd.radec, s);
   }
@@ -279,10 +285,23 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
 
 constexpr Slots NO_SLOTS{-1, -1, -1, -1};
 
+// Coarse index of B's sorted keys: one entry per 2^shift keys, at most 2^18
+struct KeyIndex {
+  int shift;
+  uint32_t T;
+};
+KeyIndex key_index_dims(const Geom& g) {
+  const int kb = key_bits(g);
+  const int shift = std::max(6, kb - 18);
+  return KeyIndex{shift, (uint32_t)((1ull << std::max(kb - shift, 0)) + 1)};
+}
+
 struct MatchWs {
   uint32_t* lb;
+  uint32_t* kidx;
   GroupRanges* ranges;
   int32_t* zmarg;
+  double* zdelta;
   uint32_t* zstartB;  // nullptr: computed here into zstart_buf
   uint32_t* zstart_buf;
   uint2* band;
@@ -321,7 +340,8 @@ void carve_regions(Carve& c, Regions& r, const Caps& k, bool sep) {
   r.pairs = c.take<uint2>((size_t)NREG * k.stage);
   r.sep = sep ? c.take<double>((size_t)NREG * k.stage) : nullptr;
   r.Sc = k.cand;
-  r.cand = k.cand ? c.take<uint2>((size_t)NREG * k.cand) : nullptr;
+  r.cand = k.cand ? c.take<Cand>((size_t)NREG * k.cand) : nullptr;
+  r.cpre = c.take<unsigned long long>((size_t)NREG + 1);
 }
 
 // True when the call must run again: its band list overflowed, a candidate
@@ -363,16 +383,17 @@ OutArgs out_args(hlc_pair* pairs, double* sep, uint64_t cap, uint2* band, uint64
 // Everything after the partition: ranges, match, certification.
 void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_arcsec, bool fp32,
            bool skip_halo_a, bool self_only, const Radii& rad, const MatchWs& w,
-           hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, hipStream_t s) {
+           hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, int filter_items, hipStream_t s) {
   Thresholds th = thresholds(r_arcsec);
-  launch_zone_tables(g, w.zmarg, s);
+  launch_zone_tables(g, w.zmarg, w.zdelta, s);
   const uint32_t* zstart = w.zstartB;
   if (!zstart) {
     launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, s);
     zstart = w.zstart_buf;
   }
-  launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, w.lb, s);
-  launch_ranges(A.keys, A.cnt, w.lb, B.keys, zstart, w.zmarg, g, w.ranges, s);
+  const KeyIndex ki = key_index_dims(g);
+  launch_key_index(B.keys, B.cnt, ki.shift, ki.T, w.kidx, s);
+  launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, s);
   if (prof) (void)hipEventRecord(dev.ev[8], s);
   MatchArgs ma{};
   ma.ranges = w.ranges;
@@ -388,6 +409,11 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.keysA = A.keys;
   ma.keysB = B.keys;
   ma.thr32 = th.thr32;
+  if (!(fp32 ? (const void*)A.r32 : (const void*)A.r64)) {
+    ma.valsA = A.vals;
+    ma.srcA64 = A.src64;
+    ma.srcA32 = A.src32;
+  }
   ma.geom = g;
   ma.H_lo = th.H_lo;
   ma.H_hi = th.H_hi;
@@ -399,7 +425,7 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.hp_order = -1;
   const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
   launch_regions_reset(oa, s);
-  launch_filter(ma, oa, fp32, s);
+  launch_filter(ma, oa, fp32, filter_items, s);
   if (prof) (void)hipEventRecord(dev.ev[9], s);
   launch_cand(ma, oa, fp32, s);
   launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, s);
@@ -414,6 +440,8 @@ size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, 
   w.lb = c.take<uint32_t>(nA);
   w.ranges = c.take<GroupRanges>((nA + GROUP - 1) / GROUP);
   w.zmarg = c.take<int32_t>((size_t)g.nz);
+  w.kidx = c.take<uint32_t>(key_index_dims(g).T);
+  w.zdelta = c.take<double>((size_t)g.nz);
   w.zstart_buf = need_zstart ? c.take<uint32_t>((size_t)g.nz + 1) : nullptr;
   w.zstartB = nullptr;
   w.band = c.take<uint2>(band_cap);
@@ -422,14 +450,15 @@ size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, 
   return c.off;
 }
 
-// cap entries; n_src > 0 also carves the per-source records of the keygen
-void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src = 0) {
+// cap entries; n_src > 0 also carves the per-source records of the keygen;
+// without `layout` no sorted records are carved (the side is read in place)
+void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src = 0, bool layout = true) {
   cap = std::max(cap, 1u);
   sd.keys = c.take<uint32_t>(cap);
   sd.vals = c.take<uint32_t>(cap);
-  sd.r64 = l64 ? c.take<Rec64>(cap) : nullptr;
-  sd.r32 = l32 ? c.take<Rec32>(cap) : nullptr;
-  sd.radec = l32 ? c.take<double2>(cap) : nullptr;
+  sd.r64 = (l64 && layout) ? c.take<Rec64>(cap) : nullptr;
+  sd.r32 = (l32 && layout) ? c.take<Rec32>(cap) : nullptr;
+  sd.radec = (l32 && layout) ? c.take<double2>(cap) : nullptr;
   sd.src64 = (l64 && n_src) ? c.take<Rec64>(n_src) : nullptr;
   sd.src32 = (l32 && n_src) ? c.take<SrcRec32>(n_src) : nullptr;
 }
@@ -507,7 +536,8 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   SortScratch sc;
   MatchWs w;
   auto lay = [&](Carve& c) {
-    if (!self) carve_side(c, A, nA, !fp32, fp32, nA);
+    // A is read in place: the filter gathers its records itself
+    if (!self) carve_side(c, A, nA, !fp32, fp32, nA, false);
     carve_side(c, B, 2 * nB, !fp32, fp32, nB);
     carve_sort(c, sc, std::max(nA, 2 * nB));
     carve_match_ws(c, w, nA, g, caps, true);
@@ -533,7 +563,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, sc, 1u, A, slA, s));
   }
   match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, w, out_pairs,
-        (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, s);
+        (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, tuned_items(o), s);
   HLC_CHECK(read_counters(*dev, s, prof));
 
   const Counters& h = *dev->cnt_host;
@@ -780,7 +810,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       const OutArgs oa = out_args(out_pairs, (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec,
                                   (uint64_t)opts->capacity, w.band, w.band_cap, w.reg, dev->cnt);
       launch_regions_reset(oa, s);
-      launch_filter(ma, oa, false, s);
+      launch_filter(ma, oa, false, 1, s);
       launch_cand(ma, oa, false, s);
       launch_certify(a_ra, a_dec, b_ra, b_dec, r_arcsec, th.H_lo, th.H_hi, Radii{nullptr, nullptr, 0.0}, oa, s);
       launch_compact(oa, s);
@@ -939,7 +969,8 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       launch_zero_counters(dev->cnt, s);
       match(*dev, A->side, B->side, g, r_arcsec, fp32, true, false, Radii{nullptr, nullptr, 0.0}, w,
             out_pairs,
-            (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec, (uint64_t)opts->capacity, prof, s);
+            (opts->flags & HLC_NO_SEP) ? nullptr : out_sep_arcsec, (uint64_t)opts->capacity, prof,
+            tuned_items(opts), s);
       HLC_CHECK(read_counters(*dev, s, prof));
       const Counters& h = *dev->cnt_host;
       if (regrow(*dev, h, (uint64_t)opts->capacity, caps)) continue;

@@ -44,7 +44,7 @@ void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, u
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
                 hipStream_t s, bool from_alt = false);
 
-void launch_zone_tables(const Geom& g, int32_t* zmarg, hipStream_t s);
+void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s);
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s);
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
@@ -53,9 +53,12 @@ void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, 
                      Rec32* rec, double2* radec, hipStream_t s);
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
                      const DevCount& nb, uint32_t* lb, hipStream_t s);
-void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
-                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
-                   GroupRanges* out, hipStream_t s);
+// idx[i] = first position of the sorted keys with key >= i << shift, i < T
+void launch_key_index(const uint32_t* keys, const DevCount& n, int shift, uint32_t T, uint32_t* idx,
+                      hipStream_t s);
+void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* kidx, int kshift, uint32_t kT,
+                   const uint32_t* keysB, const uint32_t* zstartB, const int32_t* zmarg, const double* zdelta,
+                   const Geom& g, GroupRanges* out, hipStream_t s);
 
 // ---- match.hip -------------------------------------------------------------
 // Output allocation. A single counter bumped by every wave serialises at the
@@ -66,14 +69,25 @@ void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb
 constexpr int NREG = 256;
 constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
 
+// A staged filter candidate: everything the certification needs of the A
+// entry travels with it, so the certification reads nothing of A.
+//   (u0, u1, u2): A's FP64 unit vector (FP64 form) or (ra, dec, 0) (FP32 form)
+//   ia: A's original index (paper-scheme emulation: A's sorted position)
+//   bp: B's sorted position
+struct Cand {
+  double u0, u1, u2;
+  uint32_t ia, bp;
+};
+
 struct Regions {
   unsigned long long* fill;     // NREG * REG_STRIDE; fill[k * REG_STRIDE] = pairs sent to region k
   unsigned long long* cfill;    // NREG * REG_STRIDE; candidates sent to region k
   uint2* pairs;                 // NREG * S staging
   double* sep;                  // NREG * S staging, or nullptr
   unsigned long long S;         // pair slots per region
-  uint2* cand;                  // NREG * Sc staging of (A position, B position), or nullptr
+  Cand* cand;                   // NREG * Sc staged candidates, or nullptr
   unsigned long long Sc;        // candidate slots per region (0: candidates are only counted)
+  unsigned long long* cpre;     // NREG + 1: exclusive prefix of the staged candidate counts
 };
 
 struct OutArgs {
@@ -139,6 +153,11 @@ struct MatchArgs {
   const double2* radecA;
   const double2* radecB;
   float thr32;                  // chord^2 bound covering the FP32 rounding
+  // A read in place (recA64 / recA32 / radecA unused): entry p's record is
+  // the keygen's per-source record of source valsA[p]
+  const uint32_t* valsA;
+  const Rec64* srcA64;
+  const SrcRec32* srcA32;
   const uint32_t* keysA;
   const uint32_t* keysB;
   Geom geom;
@@ -171,7 +190,7 @@ void launch_regions_reset(const OutArgs& o, hipStream_t s);
 void launch_compact(const OutArgs& o, hipStream_t s);
 // the filter writes candidates into the candidate regions; the
 // certification kernel decides them and writes pairs and the band list
-void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s);
+void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, int items_per_wave, hipStream_t s);
 void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s);
 // Re-decide the band list from the original coordinates: FP64 haversine,
 // then double-double inside the FP64 band.

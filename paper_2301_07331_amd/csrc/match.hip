@@ -53,7 +53,7 @@ namespace {
 constexpr int MT = 256;     // threads per block
 constexpr int WAVES = MT / 64;
 constexpr int QCAP = 256;   // per-wave candidate queue, staged above QCAP - 64
-constexpr unsigned long long CAND_BLOCKS_MAX = 65536;  // grid cap of the certification walk
+constexpr unsigned long long CAND_BLOCKS_MAX = 8192;  // grid cap of the certification walk
 
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
   // consecutive logical blocks on the same XCD (dispatch is round-robin over 8)
@@ -100,7 +100,7 @@ __device__ inline void emit_band(bool band, uint32_t ia, uint32_t ib, const OutA
 }
 
 // ---------------------------------------------------------------------------
-// certification of one candidate (A position, B position)
+// certification of one staged candidate
 // ---------------------------------------------------------------------------
 struct Verdict {
   bool in, band;
@@ -109,31 +109,26 @@ struct Verdict {
 };
 
 template <bool HP>
-__device__ inline Verdict certify64(const MatchArgs& a, uint2 ent) {
+__device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
   Verdict v{false, false, 0u, 0u, 0.0};
-  const Rec64 A = a.recA64[ent.x];
-  const Rec64 B = a.recB64[ent.y];
-  const double dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+  const Rec64 B = a.recB64[c.bp];
+  const double dx = c.u0 - B.x, dy = c.u1 - B.y, dz = c.u2 - B.z;
   const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  v.ia = A.idx & IDX_MASK;
+  v.ia = HP ? (a.recA64[c.ia].idx & IDX_MASK) : c.ia;
   v.ib = B.idx & IDX_MASK;
-  // a group straddling two zones (pixels) also scans the other one, whose B
-  // entries include copies of B sources this A meets in its own zone
-  // (pixel): only entries of the A entry's own zone (pixel) count
-  bool keep = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
+  bool keep = !a.self_only || v.ia < v.ib;
   if constexpr (HP) {
     // paper-scheme emulation: count the pair in the smallest shared pixel
     uint32_t pa[5], pb[5];
-    const double2 ca = a.radecA[ent.x], cb = a.radecB[ent.y];
+    const double2 ca = a.radecA[c.ia], cb = a.radecB[c.bp];
     const int na_ = hp_quad(a.hp_order, ca.x, ca.y, a.hp_R, pa);
     const int nb_ = hp_quad(a.hp_order, cb.x, cb.y, a.hp_R, pb);
     uint32_t first = 0xffffffffu;
     for (int u = 0; u < na_; ++u)
       for (int w = 0; w < nb_; ++w)
         if (pa[u] == pb[w] && pa[u] < first) first = pa[u];
-    keep = keep && first == a.keysA[ent.x];
+    keep = keep && first == a.keysA[c.ia];
   }
-  keep = keep && (!a.self_only || v.ia < v.ib);
   double tlo = a.t_lo64, thi = a.t_hi64;
   if (a.a_err) pair_chord_thr(pair_radius(a, v.ia, v.ib), tlo, thi);
   v.in = keep && d2 <= tlo;
@@ -142,15 +137,13 @@ __device__ inline Verdict certify64(const MatchArgs& a, uint2 ent) {
   return v;
 }
 
-__device__ inline Verdict certify32(const MatchArgs& a, uint2 ent) {
+__device__ inline Verdict certify32(const MatchArgs& a, const Cand& c) {
   Verdict v{false, false, 0u, 0u, 0.0};
-  const double2 pa = a.radecA[ent.x];
-  const double2 pb = a.radecB[ent.y];
-  v.ia = a.recA32[ent.x].idx & IDX_MASK;
-  v.ib = a.recB32[ent.y].idx & IDX_MASK;
-  const double h = haversine64(pa.x, pa.y, pb.x, pb.y);
-  const bool same_zone = ((a.keysA[ent.x] ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
-  const bool keep = same_zone && (!a.self_only || v.ia < v.ib);
+  const double2 pb = a.radecB[c.bp];
+  v.ia = c.ia;
+  v.ib = a.recB32[c.bp].idx & IDX_MASK;
+  const double h = haversine64(c.u0, c.u1, pb.x, pb.y);
+  const bool keep = !a.self_only || v.ia < v.ib;
   double Hlo = a.H_lo, Hhi = a.H_hi;
   if (a.a_err) pair_hav_thr(pair_radius(a, v.ia, v.ib), Hlo, Hhi);
   v.in = keep && h < Hlo;
@@ -159,56 +152,95 @@ __device__ inline Verdict certify32(const MatchArgs& a, uint2 ent) {
   return v;
 }
 
-// Every staged candidate, regions in order: block-wide prefix of the region
-// fills in LDS, then a grid-stride walk over the concatenation.
-template <bool F32, bool HP>
+// Exclusive prefix of the staged candidate counts (region order), for k_cand.
+__global__ __launch_bounds__(NREG) void k_cand_prefix(Regions reg) {
+  __shared__ unsigned long long s[NREG];
+  const uint32_t t = threadIdx.x;
+  const unsigned long long f = reg.cfill[t * REG_STRIDE];
+  s[t] = f < reg.Sc ? f : reg.Sc;
+  __syncthreads();
+  for (uint32_t d = 1; d < NREG; d <<= 1) {
+    const unsigned long long x = t >= d ? s[t - d] : 0ull;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  reg.cpre[t + 1] = s[t];
+  if (t == 0) reg.cpre[0] = 0ull;
+}
+
+// Every staged candidate, regions in order: ITEMS per thread, their loads
+// in flight together, then the emissions.
+constexpr int CAND_ITEMS = 2;
+
+template <bool F32, bool HP, int ITEMS>
 __global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
   __shared__ unsigned long long s_pre[NREG + 1];
   const uint32_t t = threadIdx.x;
-  if (t < NREG) {
-    const unsigned long long f = o.reg.cfill[t * REG_STRIDE];
-    s_pre[t + 1] = f < o.reg.Sc ? f : o.reg.Sc;
-  }
-  if (t == 0) s_pre[0] = 0ull;
+  for (uint32_t k = t; k <= NREG; k += blockDim.x) s_pre[k] = o.reg.cpre[k];
   __syncthreads();
-  // inclusive scan of s_pre[1..NREG] (Hillis-Steele; NREG = blockDim.x)
-  for (uint32_t d = 1; d < NREG; d <<= 1) {
-    unsigned long long x = 0ull;
-    if (t < NREG && t >= d) x = s_pre[t + 1 - d];
-    __syncthreads();
-    if (t < NREG) s_pre[t + 1] += x;
-    __syncthreads();
-  }
   const unsigned long long total = s_pre[NREG];
-  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const unsigned long long tile = (unsigned long long)ITEMS * blockDim.x;
   // uniform trip count so every lane of a wave takes part in the ballots
-  for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < total; base += stride) {
-    const unsigned long long i = base + t;
-    Verdict v{false, false, 0u, 0u, 0.0};
-    if (i < total) {
-      uint32_t lo = 0, hi = NREG;  // region k with s_pre[k] <= i < s_pre[k + 1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= i) lo = mid; else hi = mid;
+  for (unsigned long long base = (unsigned long long)blockIdx.x * tile; base < total;
+       base += (unsigned long long)gridDim.x * tile) {
+    Verdict v[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const unsigned long long i = base + (unsigned long long)j * blockDim.x + t;
+      v[j] = Verdict{false, false, 0u, 0u, 0.0};
+      if (i < total) {
+        uint32_t lo = 0, hi = NREG;  // region k with s_pre[k] <= i < s_pre[k + 1]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= i) lo = mid; else hi = mid;
+        }
+        const Cand c = o.reg.cand[(unsigned long long)lo * o.reg.Sc + (i - s_pre[lo])];
+        if constexpr (F32) v[j] = certify32(a, c);
+        else v[j] = certify64<HP>(a, c);
       }
-      const uint2 ent = o.reg.cand[(unsigned long long)lo * o.reg.Sc + (i - s_pre[lo])];
-      if constexpr (F32) v = certify32(a, ent);
-      else v = certify64<HP>(a, ent);
     }
-    emit_wave(v.in, v.ia, v.ib, v.sep, o);
-    emit_band(v.band, v.ia, v.ib, o);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      emit_wave(v[j].in, v[j].ia, v[j].ib, v[j].sep, o);
+      emit_band(v[j].band, v[j].ia, v[j].ib, o);
+    }
   }
 }
 
-// A wave's queue appended to its candidate region (one atomic).
-__device__ inline void stage_candidates(const OutArgs& o, const uint2* q, uint32_t qn) {
+// A wave's queue of (A position, B position) appended to its candidate
+// region as self-contained records. Every queued A position belongs to the
+// wave's current item, so its A data comes from the owning lane (A position
+// mod 64). Entries whose B record lies in another zone (pixel) than the A
+// entry are dropped here: a group straddling two zones also scans the other
+// one, whose B entries include copies of sources the A entry meets in its
+// own zone. One atomic per 64 entries.
+// Per-lane A data of the current item, kept in LDS (not registers) until a
+// candidate of that lane is staged.
+struct ALane {
+  double u0, u1, u2;
+  uint32_t ia, key;
+};
+
+__device__ inline void stage_candidates(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn,
+                                        const ALane* al) {
   const uint32_t k = wave_region();
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(&o.reg.cfill[k * REG_STRIDE], (unsigned long long)qn);
-  base = __shfl(base, 0);
-  for (uint32_t e = lane_id(); e < qn; e += 64) {
-    const unsigned long long slot = base + e;
-    if (slot < o.reg.Sc) o.reg.cand[(unsigned long long)k * o.reg.Sc + slot] = q[e];
+  const uint32_t lane = lane_id();
+  for (uint32_t b0 = 0; b0 < qn; b0 += 64) {
+    const uint32_t e = b0 + lane;
+    const uint2 ent = e < qn ? q[e] : make_uint2(lane, 0u);
+    const ALane& A = al[ent.x & 63u];
+    const bool keep = e < qn && ((A.key ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
+    const uint64_t m = __ballot(keep);
+    if (m == 0) continue;
+    const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(&o.reg.cfill[k * REG_STRIDE], (unsigned long long)__popcll(m));
+    base = __shfl(base, (int)leader);
+    if (keep) {
+      const unsigned long long slot = base + rank_in(m);
+      if (slot < o.reg.Sc) o.reg.cand[(unsigned long long)k * o.reg.Sc + slot] = Cand{A.u0, A.u1, A.u2, A.ia, ent.y};
+    }
   }
 }
 
@@ -222,24 +254,12 @@ struct Flat {
   uint32_t total;
 };
 
-__device__ inline Flat flatten(const GroupRanges* R) {
-  Flat f{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-  if (R == nullptr) return f;
-  const uint32_t n = R->count;
-  auto len = [&](int t) { return (uint32_t)t < n && R->end[t] > R->start[t] ? R->end[t] - R->start[t] : 0u; };
-  f.s0 = R->start[0];
-  f.s1 = R->start[1];
-  f.s2 = R->start[2];
-  f.s3 = R->start[3];
-  f.p1 = len(0);
-  f.p2 = f.p1 + len(1);
-  f.p3 = f.p2 + len(2);
-  f.total = f.p3 + len(3);
-  return f;
-}
-
 __device__ inline uint32_t flat_pos(const Flat& f, uint32_t t) {
-  return t < f.p1 ? f.s0 + t : t < f.p2 ? f.s1 + (t - f.p1) : t < f.p3 ? f.s2 + (t - f.p2) : f.s3 + (t - f.p3);
+  uint32_t pos = f.s0 + t;
+  pos = t >= f.p1 ? f.s1 + (t - f.p1) : pos;
+  pos = t >= f.p2 ? f.s2 + (t - f.p2) : pos;
+  pos = t >= f.p3 ? f.s3 + (t - f.p3) : pos;
+  return pos;
 }
 
 template <typename V>
@@ -259,82 +279,188 @@ __device__ inline Vec3<typename std::conditional<F32, float, double>::type> load
   }
 }
 
-// sixteen tests: bit N of mask <- |a - b_N|^2 <= thr, b_N the record of lane
-// N of this lane's row
+// up to sixteen tests: bit N of mask <- |a - b_N|^2 <= thr, b_N the record of
+// lane N of this lane's row; steps from nmax (wave-uniform: no row has a
+// record there) on are skipped
 template <int N, typename V>
-__device__ inline void tests(const Vec3<V>& A, const Vec3<V>& B, V thr, uint32_t& mask) {
+__device__ inline void tests(const Vec3<V>& A, const Vec3<V>& B, V thr, uint32_t nmax, uint32_t& mask) {
+  if (N >= nmax) return;
   const V dx = A.x - row_bcast<N>(B.x);
   const V dy = A.y - row_bcast<N>(B.y);
   const V dz = A.z - row_bcast<N>(B.z);
   const V d2 = fma(dx, dx, fma(dy, dy, dz * dz));
   mask |= (d2 <= thr ? 1u : 0u) << N;
-  if constexpr (N + 1 < GROUP) tests<N + 1, V>(A, B, thr, mask);
+  if constexpr (N + 1 < GROUP) tests<N + 1, V>(A, B, thr, nmax, mask);
 }
 
+// Loads of one work item (four groups, one per row) that do not depend on
+// other loads: the group's ranges and the A entry's source index.
+struct ItemHead {
+  uint32_t s[MAXR], e[MAXR], n;
+  uint32_t grp, a_pos, va;
+  bool a_ok;
+};
+
+__device__ inline ItemHead item_head(const MatchArgs& a, uint32_t item, uint32_t row, uint32_t l16, uint32_t na,
+                                     uint32_t ngroups) {
+  ItemHead h;
+  h.grp = item * 4u + row;
+  h.a_pos = h.grp * GROUP + l16;
+  const bool grp_ok = h.grp < ngroups;
+  h.a_ok = grp_ok && h.a_pos < na;
+  h.n = 0u;
+#pragma unroll
+  for (int t = 0; t < MAXR; ++t) h.s[t] = h.e[t] = 0u;
+  if (grp_ok) {
+    const GroupRanges* R = a.ranges + h.grp;
+    h.n = R->count;
+#pragma unroll
+    for (int t = 0; t < MAXR; ++t) {
+      h.s[t] = R->start[t];
+      h.e[t] = R->end[t];
+    }
+  }
+  h.va = (h.a_ok && a.valsA) ? a.valsA[h.a_pos] : 0u;
+  return h;
+}
+
+__device__ inline Flat flatten(const ItemHead& h) {
+  auto len = [&](int t) { return (uint32_t)t < h.n && h.e[t] > h.s[t] ? h.e[t] - h.s[t] : 0u; };
+  Flat f;
+  f.s0 = h.s[0];
+  f.s1 = h.s[1];
+  f.s2 = h.s[2];
+  f.s3 = h.s[3];
+  f.p1 = len(0);
+  f.p2 = f.p1 + len(1);
+  f.p3 = f.p2 + len(2);
+  f.total = f.p3 + len(3);
+  return f;
+}
+
+// Persistent: wave w of W takes items w, w + W, ... (an item is four groups,
+// one per 16-lane row). The next item's ranges and A index are loaded
+// while the current one is tested.
 template <bool F32>
 __global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
   using V = typename std::conditional<F32, float, double>::type;
   __shared__ uint2 s_q[WAVES][QCAP];
+  __shared__ ALane s_a[WAVES][64];
   const uint32_t lane = lane_id();
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t row = lane >> 4, l16 = lane & 15u;
+  // consecutive logical blocks on one XCD: neighbouring groups share B
+  // records in its L2
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t grp = (blk * WAVES + w) * 4u + row;
+  const uint32_t W = gridDim.x * WAVES;
   uint2* q = s_q[w];
   uint32_t qn = 0;
 
   const uint32_t na = a.na.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
-  const bool grp_ok = grp < ngroups;
-  const Flat f = flatten(grp_ok ? a.ranges + grp : nullptr);
-  const uint32_t a_pos = grp * GROUP + l16;
-  bool a_ok = grp_ok && a_pos < na;
+  const uint32_t nitems = (ngroups + 3u) / 4u;
   const V far = (V)1e30;
-  Vec3<V> A{far, far, far};
-  if (a_ok) {
-    A = load_rec<F32>(a, false, a_pos);
-    const uint32_t idx = F32 ? a.recA32[a_pos].idx : a.recA64[a_pos].idx;
-    if (a.skip_halo_a && (idx & HALO_BIT)) a_ok = false;
-  }
-  if (!a_ok) A = Vec3<V>{-far, -far, -far};
   V thr;
   if constexpr (F32) thr = a.thr32;
   else thr = a.t_hi64;
 
-  // chunk c of the row covers items [16c, 16c + 16) of the concatenation
-  const uint32_t nch = (f.total + 15u) >> 4;
-  uint32_t t = l16;
-  uint32_t bp = t < f.total ? flat_pos(f, t) : 0u;
-  Vec3<V> B{far, far, far};
-  if (t < f.total) B = load_rec<F32>(a, true, bp);
-  for (uint32_t c = 0; __ballot(c < nch); ++c) {
-    // next chunk's record in flight while this one is tested
-    const uint32_t tn = t + GROUP;
-    const uint32_t bpn = tn < f.total ? flat_pos(f, tn) : 0u;
-    Vec3<V> Bn{far, far, far};
-    if (tn < f.total) Bn = load_rec<F32>(a, true, bpn);
-
-    uint32_t mask = 0u;
-    tests<0, V>(A, B, thr, mask);
-    // drain the hits into the queue, lowest bit first
-    while (__ballot(mask != 0u)) {
-      const bool has = mask != 0u;
-      const uint32_t bit = has ? (uint32_t)__builtin_ctz(mask) : 0u;
-      const uint32_t bpos = (uint32_t)__shfl((int)bp, (int)((lane & 48u) | bit));
-      const uint64_t m = __ballot(has);
-      if (has) q[qn + rank_in(m)] = make_uint2(a_pos, bpos);
-      qn += (uint32_t)__popcll(m);
-      mask &= mask - 1u;
-      if (qn > QCAP - 64) {
-        stage_candidates(o, q, qn);
-        qn = 0;
+  uint32_t item = blk * WAVES + w;
+  ItemHead head = item_head(a, item, row, l16, na, ngroups);
+  while (__builtin_amdgcn_readfirstlane(item) < nitems) {
+    const ItemHead cur = head;
+    const uint32_t next = item + W;
+    // stage 1 of this item: its first B chunk and its A record
+    const Flat f = flatten(cur);
+    uint32_t t = l16;
+    uint32_t bp = t < f.total ? flat_pos(f, t) : 0u;
+    Vec3<V> B{far, far, far};
+    if (t < f.total) B = load_rec<F32>(a, true, bp);
+    bool a_ok = cur.a_ok;
+    Vec3<V> A{-far, -far, -far};
+    // what a staged candidate carries of this lane's A entry
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    uint32_t ia = 0u, keyA = 0u;
+    if (a_ok) {
+      uint32_t idx;
+      keyA = a.keysA[cur.a_pos];
+      if (a.valsA) {
+        idx = cur.va;
+        if constexpr (F32) {
+          const SrcRec32 r = a.srcA32[idx & IDX_MASK];
+          A = Vec3<V>{r.x, r.y, r.z};
+          u0 = r.ra;
+          u1 = r.dec;
+        } else {
+          const Rec64 r = a.srcA64[idx & IDX_MASK];
+          A = Vec3<V>{r.x, r.y, r.z};
+          u0 = r.x;
+          u1 = r.y;
+          u2 = r.z;
+        }
+      } else {
+        A = load_rec<F32>(a, false, cur.a_pos);
+        idx = F32 ? a.recA32[cur.a_pos].idx : a.recA64[cur.a_pos].idx;
+        if constexpr (F32) {
+          const double2 p = a.radecA[cur.a_pos];
+          u0 = p.x;
+          u1 = p.y;
+        } else {
+          u0 = A.x;
+          u1 = A.y;
+          u2 = A.z;
+        }
+      }
+      ia = a.hp_order >= 0 ? cur.a_pos : (idx & IDX_MASK);
+      if (a.skip_halo_a && (idx & HALO_BIT)) {
+        a_ok = false;
+        A = Vec3<V>{-far, -far, -far};
       }
     }
-    t = tn;
-    bp = bpn;
-    B = Bn;
+    s_a[w][lane] = ALane{u0, u1, u2, ia, keyA};
+    // stage 0 of the next item, in flight while this one is tested
+    head = item_head(a, next, row, l16, na, ngroups);
+
+    // chunk c of the row covers items [16c, 16c + 16) of the concatenation
+    const uint32_t nch = (f.total + 15u) >> 4;
+    for (uint32_t c = 0; __ballot(c < nch); ++c) {
+      // next chunk's record in flight while this one is tested
+      const uint32_t tn = t + GROUP;
+      const uint32_t bpn = tn < f.total ? flat_pos(f, tn) : 0u;
+      Vec3<V> Bn{far, far, far};
+      if (tn < f.total) Bn = load_rec<F32>(a, true, bpn);
+
+      // records in this chunk: the largest count over the wave's four rows
+      uint32_t nrow = f.total > t - l16 ? min(f.total - (t - l16), (uint32_t)GROUP) : 0u;
+      nrow = max(nrow, (uint32_t)__shfl_xor((int)nrow, 16));
+      nrow = max(nrow, (uint32_t)__shfl_xor((int)nrow, 32));
+      const uint32_t nmax = __builtin_amdgcn_readfirstlane(nrow);
+      uint32_t mask = 0u;
+      tests<0, V>(A, B, thr, nmax, mask);
+      // drain the hits into the queue, lowest bit first
+      while (__ballot(mask != 0u)) {
+        const bool has = mask != 0u;
+        const uint32_t bit = has ? (uint32_t)__builtin_ctz(mask) : 0u;
+        const uint32_t bpos = (uint32_t)__shfl((int)bp, (int)((lane & 48u) | bit));
+        const uint64_t m = __ballot(has);
+        if (has) q[qn + rank_in(m)] = make_uint2(cur.a_pos, bpos);
+        qn += (uint32_t)__popcll(m);
+        mask &= mask - 1u;
+        if (qn > QCAP - 64) {
+          stage_candidates(a, o, q, qn, s_a[w]);
+          qn = 0;
+        }
+      }
+      t = tn;
+      bp = bpn;
+      B = Bn;
+    }
+    // the queue holds this item's entries only (their A data is in its lanes)
+    if (qn) {
+      stage_candidates(a, o, q, qn, s_a[w]);
+      qn = 0;
+    }
+    item = next;
   }
-  if (qn) stage_candidates(o, q, qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,10 +569,12 @@ void launch_regions_reset(const OutArgs& o, hipStream_t s) { k_regions_reset<<<1
 
 void launch_compact(const OutArgs& o, hipStream_t s) { k_compact<<<NREG * CPB, 256, 0, s>>>(o); }
 
-void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s) {
+void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, int items_per_wave, hipStream_t s) {
   const uint32_t ngroups = (a.na.cap + GROUP - 1) / GROUP;
   if (ngroups == 0) return;
-  const uint32_t blocks = (ngroups + 4 * WAVES - 1) / (4 * WAVES);
+  const uint32_t items = (ngroups + 3) / 4;
+  const uint32_t per_block = WAVES * (uint32_t)std::max(items_per_wave, 1);
+  const uint32_t blocks = (items + per_block - 1) / per_block;
   if (fp32) k_filter<true><<<blocks, MT, 0, s>>>(a, o);
   else k_filter<false><<<blocks, MT, 0, s>>>(a, o);
 }
@@ -455,10 +583,12 @@ void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s)
   // one candidate per thread when the staging is full; the walk is
   // grid-stride beyond that
   const unsigned long long slots = (unsigned long long)NREG * o.reg.Sc;
-  const uint32_t blocks = (uint32_t)std::min<unsigned long long>(CAND_BLOCKS_MAX, std::max(1ull, (slots + 255) / 256));
-  if (fp32) k_cand<true, false><<<blocks, 256, 0, s>>>(a, o);
-  else if (a.hp_order >= 0) k_cand<false, true><<<blocks, 256, 0, s>>>(a, o);
-  else k_cand<false, false><<<blocks, 256, 0, s>>>(a, o);
+  const uint32_t blocks = (uint32_t)std::min<unsigned long long>(
+      CAND_BLOCKS_MAX, std::max(1ull, (slots + 256 * CAND_ITEMS - 1) / (256 * CAND_ITEMS)));
+  k_cand_prefix<<<1, NREG, 0, s>>>(o.reg);
+  if (fp32) k_cand<true, false, CAND_ITEMS><<<blocks, 256, 0, s>>>(a, o);
+  else if (a.hp_order >= 0) k_cand<false, true, 1><<<blocks, 256, 0, s>>>(a, o);
+  else k_cand<false, false, CAND_ITEMS><<<blocks, 256, 0, s>>>(a, o);
 }
 
 void launch_certify(const double* a_ra, const double* a_dec, const double* b_ra,

@@ -303,8 +303,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 // ---------------------------------------------------------------------------
 // zone / cell tables
 // ---------------------------------------------------------------------------
-// RA margin of each zone in bins (-1: the zone is scanned as a whole ring)
-__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg) {
+// Per zone: the RA half-width (deg, padded outward) of a window of radius
+// r around any of its sources, and that width in bins plus one (-1 for
+// both: the zone is scanned as a whole ring)
+__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double* __restrict__ zdelta) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (uint32_t)g.nz) {
     const int32_t z = (int32_t)i;
@@ -314,6 +316,7 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg) {
     // rounding of the zone formula)
     double dstar = fmin(fmax(fabs(lo), fabs(hi)) + 1e-9, 90.0);
     int32_t m = -1;  // -1: whole zone ring
+    double dz = -1.0;
     if (dstar + g.rpad_deg < 90.0) {
       double ss, cs, sd, cd;
       sincos_deg(g.rpad_deg, &ss, &cs);
@@ -321,11 +324,18 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg) {
       double x = ss / cd;
       if (x < 0.99) {
         double delta = asin(x) * (180.0 / M_PI) * (1.0 + 1e-9) + 1e-12;
-        double mm = ceil(delta * g.bin_scale) + 2.0;
-        if (2.0 * mm + 1.0 < (double)g.nbins) m = (int32_t)mm;
+        // floor(ra * scale) is monotone in ra, and a shift by delta moves it
+        // by at most ceil(delta * scale) + 1 bins (one for the rounding of
+        // the product)
+        double mm = ceil(delta * g.bin_scale) + 1.0;
+        if (2.0 * mm + 1.0 < (double)g.nbins) {
+          m = (int32_t)mm;
+          dz = delta;
+        }
       }
     }
     zmarg[z] = m;
+    zdelta[z] = dz;
   }
 }
 
@@ -518,6 +528,41 @@ __device__ inline uint32_t gallop_upper(const uint32_t* keys, uint32_t K, uint32
   return gallop_lower(keys, K + 1u, hint, lo, hi);
 }
 
+// Coarse index of sorted keys: idx[i] = first position with key >= i << shift,
+// for i < T (T = (key space >> shift) + 1).
+__global__ void k_key_index(const uint32_t* __restrict__ keys, DevCount nc, int shift, uint32_t T,
+                            uint32_t* __restrict__ idx) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  const uint32_t n = nc.get();
+  const uint64_t K = (uint64_t)i << shift;
+  uint32_t lo = 0, hi = n;
+  if (K > 0xffffffffull) {
+    lo = n;
+  } else {
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (keys[mid] < (uint32_t)K) lo = mid + 1; else hi = mid;
+    }
+  }
+  idx[i] = lo;
+}
+
+// First position in [lo, hi) whose key is >= K (hi if none), searched only
+// between the two index entries that bracket K.
+__device__ inline uint32_t index_lower(const uint32_t* keys, const uint32_t* idx, int shift, uint32_t T,
+                                       uint64_t K, uint32_t lo, uint32_t hi) {
+  const uint64_t i = K >> shift;
+  if (i + 1 >= T) return hi;
+  uint32_t l = max(lo, idx[i]), r = min(hi, idx[i + 1]);
+  if (l > r) l = r;
+  while (l < r) {
+    const uint32_t mid = l + ((r - l) >> 1);
+    if (keys[mid] < (uint32_t)K) l = mid + 1; else r = mid;
+  }
+  return l;
+}
+
 struct RangeList {
   uint32_t s[3 * GROUP];
   uint32_t e[3 * GROUP];
@@ -535,10 +580,11 @@ struct RangeList {
 };
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keysA, DevCount nac,
-                                                const uint32_t* __restrict__ lb,
+                                                const uint32_t* __restrict__ kidx, int kshift, uint32_t kT,
                                                 const uint32_t* __restrict__ keysB,
                                                 const uint32_t* __restrict__ zstartB,
-                                                const int32_t* __restrict__ zmarg, Geom g,
+                                                const int32_t* __restrict__ zmarg,
+                                                const double* __restrict__ zdelta, Geom g,
                                                 GroupRanges* __restrict__ out) {
   const uint32_t na = nac.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
@@ -559,20 +605,31 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     const uint32_t zs = zstartB[z], ze = zstartB[z + 1];
     const int64_t bf = key_bin(g, k[q]), bl = key_bin(g, k[qe]);
     const int32_t m = zmarg[z];
-    const int64_t lo = bf - m, hi = bl + m;
+    int64_t lo = bf - m, hi = bl + m;
+    if (m >= 0) {
+      // the window from the bin edges of the segment's first and last
+      // sources: bf * width is exact (width = 360 / 2^rb), bin_of is
+      // monotone, and the half-width D is padded beyond every rounding, so
+      // every B within r of a source of bins bf..bl lies in bins lo..hi
+      const double width = 360.0 / (double)nbins;
+      const double D = zdelta[z];
+      const double x = (double)bf * width - D, y = (double)(bl + 1) * width + D;
+      lo = x >= 0.0 ? (int64_t)bin_of(g, x) : (int64_t)bin_of(g, x + 360.0) - nbins;
+      hi = y < 360.0 ? (int64_t)bin_of(g, y) : (int64_t)bin_of(g, y - 360.0) + nbins;
+    }
     if (m < 0 || hi - lo + 1 >= nbins) {
       L.add(zs, ze);
     } else if (zs < ze) {
-      uint32_t s = gallop_lower(keysB, make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)), lb[p0 + q], zs, ze);
-      uint32_t e = gallop_upper(keysB, make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)),
-                                lb[p0 + qe], zs, ze);
+      auto lower = [&](uint64_t K) { return index_lower(keysB, kidx, kshift, kT, K, zs, ze); };
+      uint32_t s = lower(make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)));
+      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) + 1);
       if (hi > nbins - 1) {  // window passes RA 360: low bins of the zone
-        uint32_t e2 = gallop_upper(keysB, make_key(g, z, (uint32_t)(hi - nbins)), zs, zs, ze);
+        uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + 1);
         L.add(zs, e2);
       }
       L.add(s, e);
       if (lo < 0) {  // window passes RA 0: high bins of the zone
-        uint32_t s2 = gallop_lower(keysB, make_key(g, z, (uint32_t)(nbins + lo)), ze, zs, ze);
+        uint32_t s2 = lower(make_key(g, z, (uint32_t)(nbins + lo)));
         L.add(s2, ze);
       }
     }
@@ -839,8 +896,8 @@ void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, u
   if (sep) (void)hipMemcpyAsync(sep, tmp_sep, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
 }
 
-void launch_zone_tables(const Geom& g, int32_t* zmarg, hipStream_t s) {
-  k_zone_tables<<<cdiv((uint32_t)g.nz, 256), 256, 0, s>>>(g, zmarg);
+void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s) {
+  k_zone_tables<<<cdiv((uint32_t)g.nz, 256), 256, 0, s>>>(g, zmarg, zdelta);
 }
 
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
@@ -867,12 +924,18 @@ void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* 
   k_merge_lb<<<blocks, MP_THREADS, 0, s>>>(keysA, na, keysB, nb, lb);
 }
 
-void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* lb, const uint32_t* keysB,
-                   const uint32_t* zstartB, const int32_t* zmarg, const Geom& g,
-                   GroupRanges* out, hipStream_t s) {
+void launch_key_index(const uint32_t* keys, const DevCount& n, int shift, uint32_t T, uint32_t* idx,
+                      hipStream_t s) {
+  k_key_index<<<cdiv(T, 256), 256, 0, s>>>(keys, n, shift, T, idx);
+}
+
+void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* kidx, int kshift, uint32_t kT,
+                   const uint32_t* keysB, const uint32_t* zstartB, const int32_t* zmarg, const double* zdelta,
+                   const Geom& g, GroupRanges* out, hipStream_t s) {
   uint32_t ngroups = cdiv(na.cap, GROUP);
   if (ngroups == 0) return;
-  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, lb, keysB, zstartB, zmarg, g, out);
+  k_ranges<<<cdiv(ngroups, 256), 256, 0, s>>>(keysA, na, kidx, kshift, kT, keysB, zstartB, zmarg, zdelta, g,
+                                                 out);
 }
 
 }  // namespace hlc

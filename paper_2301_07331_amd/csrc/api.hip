@@ -37,7 +37,16 @@ struct Device {
   size_t ws_bytes = 0;
   Counters* cnt = nullptr;        // device
   Counters* cnt_host = nullptr;   // pinned host mirror
-  hipEvent_t ev[12] = {};
+  hipEvent_t ev[13] = {};
+  // streaming form: device and pinned host arenas kept between calls
+  // (grow-only; released by hlc_shutdown)
+  void* sarena[2] = {nullptr, nullptr};
+  size_t sarena_bytes[2] = {0, 0};
+  void* harena = nullptr;
+  size_t harena_bytes = 0;
+  // A's partition runs on `side` beside B's on the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   // staging sizes that earlier calls needed (grow-only), so a repeated
   // workload does not pay the overflow re-run again
   uint64_t hint_stage = 0, hint_cand = 0;
@@ -75,6 +84,9 @@ int get_device(Device** out, int* dev_id = nullptr) {
     HLC_TRY(hipHostMalloc(&d.cnt_host, sizeof(Counters), hipHostMallocDefault));
     for (auto& e : d.ev) HLC_TRY(hipEventCreate(&e));
     HLC_TRY(hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HLC_TRY(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking));
+    HLC_TRY(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
+    HLC_TRY(hipEventCreateWithFlags(&d.join, hipEventDisableTiming));
     d.init = true;
   }
   *out = &d;
@@ -172,10 +184,12 @@ Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits
   }
   g.nbins = 1u << g.rb;
   g.bin_scale = (double)g.nbins / 360.0;
+  // spare low key bits carry the RA position inside the bin
+  g.fb = std::min(8, std::max(0, 32 - zb - g.rb));
   return g;
 }
 
-int key_bits(const Geom& g) { return ceil_log2((uint64_t)g.nz) + g.rb; }
+int key_bits(const Geom& g) { return ceil_log2((uint64_t)g.nz) + g.rb + g.fb; }
 
 struct Thresholds {
   double c_r, t_lo64, t_hi64, H_lo, H_hi;
@@ -262,14 +276,16 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
   sd.dec = dec;
   // an odd number of radix passes ends in the scratch pair unless it starts there
   const int bits = key_bits(g);
-  const bool from_alt = (radix_passes(bits) & 1) != 0;
-  launch_keygen(ra, dec, n, g, halo, err_bit, from_alt ? sc.keys_alt : sd.keys, from_alt ? sc.vals_alt : sd.vals,
-                dev.cnt, s, l64 ? sd.src64 : nullptr, l32 ? sd.src32 : nullptr);
+  const bool from_alt = (radix_passes(bits, g.fb) & 1) != 0;
+  uint32_t* kk = from_alt ? sc.keys_alt : sd.keys;
+  uint32_t* vv = from_alt ? sc.vals_alt : sd.vals;
+  launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
+                l32 ? sd.src32 : nullptr);
   mark(dev, sl.keygen, s);
   sd.n_cap = halo ? 2 * n : n;
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
   mark(dev, sl.sort_begin, s);
-  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt);
+  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, g.fb);
   mark(dev, sl.sort, s);
   if (l64 && sd.r64) {
     if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
@@ -492,15 +508,18 @@ void fill_stats(const Counters& h, int64_t na, int64_t nb, int64_t nbh, const Ge
   g_stats.zone_height_arcsec = g.h_deg * 3600.0;
 }
 
-// Stage times from the event slots: 0 start; B partition 1-4; A partition
-// 5-7 (keygen, sort, layout); 8 ranges; 9 match; 10 certify; 11 end.
+// Stage times from the event slots: 0 start; B partition 1-4 (keygen, sort
+// begin, sort, layout) on the call's stream; A partition 5-7 (keygen, sort,
+// layout) on the side stream from 0 on; 12 both partitions done; 8 ranges;
+// 9 filter; 10 certification and packing; 11 end. The two partitions
+// overlap, so their stage times add up to more than the wall time.
 void fill_times(Device& dev, bool with_partition) {
   auto el = [&](int a, int b) { return (double)elapsed(dev.ev[a], dev.ev[b]); };
   if (with_partition) {
-    g_stats.t_keygen_ms = el(0, 1) + el(4, 5);
+    g_stats.t_keygen_ms = el(0, 1) + el(0, 5);
     g_stats.t_sort_ms = el(2, 3) + el(5, 6);
     g_stats.t_layout_ms = el(3, 4) + el(6, 7);
-    g_stats.t_ranges_ms = el(7, 8);
+    g_stats.t_ranges_ms = el(12, 8);
   } else {
     g_stats.t_ranges_ms = el(0, 8);
   }
@@ -533,13 +552,16 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   const uint32_t nA = self ? 2 * nB : (uint32_t)na;
 
   Side A, B;
-  SortScratch sc;
+  SortScratch sc, scA;
   MatchWs w;
   auto lay = [&](Carve& c) {
     // A is read in place: the filter gathers its records itself
-    if (!self) carve_side(c, A, nA, !fp32, fp32, nA, false);
+    if (!self) {
+      carve_side(c, A, nA, !fp32, fp32, nA, false);
+      carve_sort(c, scA, nA);
+    }
     carve_side(c, B, 2 * nB, !fp32, fp32, nB);
-    carve_sort(c, sc, std::max(nA, 2 * nB));
+    carve_sort(c, sc, 2 * nB);
     carve_match_ws(c, w, nA, g, caps, true);
   };
   Carve sizing{nullptr};
@@ -550,18 +572,25 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
 
   if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
   launch_zero_counters(dev->cnt, s);
-  // B first: its halo count is read back before its sort; A's keygen and
-  // sort then queue behind it without another synchronisation.
+  // A's partition on the side stream, B's on the caller's; they meet before
+  // the ranges (separate sort scratch, disjoint counter fields)
   const Slots slB = prof ? Slots{1, 2, 3, 4} : NO_SLOTS;
   const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
+  if (!self) {
+    HLC_TRY(hipEventRecord(dev->fork, s));
+    HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
+    HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side));
+    HLC_TRY(hipEventRecord(dev->join, dev->side));
+  }
   HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s));
   if (self) {
     // one partition serves both roles; its halo copies are skipped as A
     for (int k : {slA.keygen, slA.sort, slA.layout}) mark(*dev, k, s);
     A = B;
   } else {
-    HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, sc, 1u, A, slA, s));
+    HLC_TRY(hipStreamWaitEvent(s, dev->join, 0));
   }
+  mark(*dev, prof ? 12 : -1, s);
   match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, w, out_pairs,
         (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, tuned_items(o), s);
   HLC_CHECK(read_counters(*dev, s, prof));
@@ -937,7 +966,7 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
   if (!A || !B) return HLC_E_INVAL;
   HLC_CHECK(check_opts(opts));
   if (!(r_arcsec > 0.0) || !(r_arcsec <= B->r_build)) return HLC_E_INVAL;
-  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb)
+  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb || A->g.fb != B->g.fb)
     return HLC_E_INVAL;
   if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
     return HLC_E_INVAL;
@@ -1434,37 +1463,40 @@ namespace hlc {
 namespace {
 
 // Resources of one streaming call, released in one place.
+// Per-call streams and events; buffers are carved from the device's
+// streaming arenas (arena 0: uploads, histogram, ring; arena 1: chunk-ordered
+// copies, sized once the halo copies are counted).
 struct StreamCall {
-  std::vector<void*> dev;
-  std::vector<void*> host;
+  Device* d = nullptr;
   hipStream_t s_copy = nullptr, s_d2h = nullptr;
   hipEvent_t ev_copy = nullptr, ev_done = nullptr, ev_d2h[2] = {nullptr, nullptr};
   ~StreamCall() {
     if (s_copy) (void)hipStreamSynchronize(s_copy);
     if (s_d2h) (void)hipStreamSynchronize(s_d2h);
-    (void)hipDeviceSynchronize();
-    for (void* p : dev) (void)hipFree(p);
-    for (void* p : host) (void)hipHostFree(p);
     for (hipEvent_t e : {ev_copy, ev_done, ev_d2h[0], ev_d2h[1]})
       if (e) (void)hipEventDestroy(e);
     if (s_copy) (void)hipStreamDestroy(s_copy);
     if (s_d2h) (void)hipStreamDestroy(s_d2h);
   }
-  template <class T>
-  int alloc(T** p, size_t n) {
-    void* q = nullptr;
-    HLC_CHECK(dev_alloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
-    dev.push_back(q);
-    *p = (T*)q;
+  // grow arena k to hold `bytes` (its previous contents are dropped)
+  int reserve(int k, size_t bytes) {
+    if (bytes <= d->sarena_bytes[k]) return HLC_OK;
+    (void)hipDeviceSynchronize();
+    if (d->sarena[k]) (void)hipFree(d->sarena[k]);
+    d->sarena[k] = nullptr;
+    d->sarena_bytes[k] = 0;
+    HLC_CHECK(dev_alloc(&d->sarena[k], bytes));
+    d->sarena_bytes[k] = bytes;
     return HLC_OK;
   }
-  template <class T>
-  int alloc_host(T** p, size_t n) {
-    void* q = nullptr;
-    if (alloc_fails(n * sizeof(T))) return HLC_E_NOMEM;
-    HLC_TRY(hipHostMalloc(&q, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
-    host.push_back(q);
-    *p = (T*)q;
+  int reserve_host(size_t bytes) {
+    if (bytes <= d->harena_bytes) return HLC_OK;
+    if (d->harena) (void)hipHostFree(d->harena);
+    d->harena = nullptr;
+    d->harena_bytes = 0;
+    if (alloc_fails(bytes)) return HLC_E_NOMEM;
+    HLC_TRY(hipHostMalloc(&d->harena, bytes, hipHostMallocDefault));
+    d->harena_bytes = bytes;
     return HLC_OK;
   }
 };
@@ -1563,6 +1595,7 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
   HLC_CHECK(get_device(&dev));
   hipStream_t s = (hipStream_t)o->stream;
   StreamCall sc;
+  sc.d = dev;
   HLC_TRY(hipStreamCreate(&sc.s_copy));
   HLC_TRY(hipStreamCreate(&sc.s_d2h));
   HLC_TRY(hipEventCreateWithFlags(&sc.ev_copy, hipEventDisableTiming));
@@ -1574,24 +1607,46 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
   const int64_t half = std::max<int64_t>(ring / 2, 1024);
   hlc_pair* d_pairs;
   double* d_sep;
-  HLC_CHECK(sc.alloc(&d_pairs, 2 * half));
-  HLC_CHECK(sc.alloc(&d_sep, 2 * half));
+  double *A_ra, *A_dec, *B_ra, *B_dec;
+  uint32_t* hist;
+  int32_t* d_cob;
+  double* d_edges;
+  unsigned long long *curA, *curB;
+  auto lay0 = [&](Carve& c) {
+    d_pairs = c.take<hlc_pair>(2 * half);
+    d_sep = c.take<double>(2 * half);
+    A_ra = c.take<double>(std::max<int64_t>(na, 1));
+    A_dec = c.take<double>(std::max<int64_t>(na, 1));
+    B_ra = c.take<double>(std::max<int64_t>(nb, 1));
+    B_dec = c.take<double>(std::max<int64_t>(nb, 1));
+    hist = c.take<uint32_t>(2 * STREAM_DEC_BINS);
+    d_cob = c.take<int32_t>(STREAM_DEC_BINS);
+    d_edges = c.take<double>(STREAM_DEC_BINS + 2);
+    curA = c.take<unsigned long long>(STREAM_DEC_BINS + 1);
+    curB = c.take<unsigned long long>(STREAM_DEC_BINS + 1);
+  };
+  {
+    Carve z{nullptr};
+    lay0(z);
+    HLC_CHECK(sc.reserve(0, z.off + 256));
+    Carve c{(char*)dev->sarena[0]};
+    lay0(c);
+  }
   hlc_pair* h_pairs[2];
   double* h_sep[2];
-  for (int k = 0; k < 2; ++k) {
-    HLC_CHECK(sc.alloc_host(&h_pairs[k], half));
-    HLC_CHECK(sc.alloc_host(&h_sep[k], half));
+  {
+    HLC_CHECK(sc.reserve_host((size_t)half * 2 * (sizeof(hlc_pair) + sizeof(double)) + 1024));
+    char* hp = (char*)dev->harena;
+    for (int k = 0; k < 2; ++k) {
+      h_pairs[k] = (hlc_pair*)hp;
+      hp += (size_t)half * sizeof(hlc_pair);
+      h_sep[k] = (double*)hp;
+      hp += (size_t)half * sizeof(double);
+    }
   }
 
   // 1. copy both catalogues in slabs; a Dec histogram of each slab runs on
   //    the compute stream while the next slab is in flight
-  double *A_ra, *A_dec, *B_ra, *B_dec;
-  HLC_CHECK(sc.alloc(&A_ra, na));
-  HLC_CHECK(sc.alloc(&A_dec, na));
-  HLC_CHECK(sc.alloc(&B_ra, nb));
-  HLC_CHECK(sc.alloc(&B_dec, nb));
-  uint32_t* hist;
-  HLC_CHECK(sc.alloc(&hist, 2 * STREAM_DEC_BINS));
   HLC_TRY(hipMemsetAsync(hist, 0, 2 * STREAM_DEC_BINS * sizeof(uint32_t), s));
   launch_zero_counters(dev->cnt, s);
   HLC_TRY(hipStreamSynchronize(s));
@@ -1652,13 +1707,6 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
   }
   ++nch;
   edges.push_back(90.0);
-  int32_t* d_cob;
-  double* d_edges;
-  unsigned long long *curA, *curB;
-  HLC_CHECK(sc.alloc(&d_cob, STREAM_DEC_BINS));
-  HLC_CHECK(sc.alloc(&d_edges, edges.size()));
-  HLC_CHECK(sc.alloc(&curA, nch));
-  HLC_CHECK(sc.alloc(&curB, nch));
   HLC_TRY(hipMemcpyAsync(d_cob, chunk_of_bin.data(), STREAM_DEC_BINS * 4, hipMemcpyHostToDevice, s));
   HLC_TRY(hipMemcpyAsync(d_edges, edges.data(), edges.size() * 8, hipMemcpyHostToDevice, s));
   // B counts per chunk including the copies for neighbouring chunks
@@ -1678,12 +1726,22 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
   // 3. chunk-ordered copies with original indices
   double *CA_ra, *CA_dec, *CB_ra, *CB_dec;
   uint32_t *CA_idx, *CB_idx;
-  HLC_CHECK(sc.alloc(&CA_ra, na));
-  HLC_CHECK(sc.alloc(&CA_dec, na));
-  HLC_CHECK(sc.alloc(&CA_idx, na));
-  HLC_CHECK(sc.alloc(&CB_ra, offB[nch]));
-  HLC_CHECK(sc.alloc(&CB_dec, offB[nch]));
-  HLC_CHECK(sc.alloc(&CB_idx, offB[nch]));
+  auto lay1 = [&](Carve& c) {
+    const size_t nA = std::max<int64_t>(na, 1), nB = std::max<uint64_t>(offB[nch], 1);
+    CA_ra = c.take<double>(nA);
+    CA_dec = c.take<double>(nA);
+    CA_idx = c.take<uint32_t>(nA);
+    CB_ra = c.take<double>(nB);
+    CB_dec = c.take<double>(nB);
+    CB_idx = c.take<uint32_t>(nB);
+  };
+  {
+    Carve z{nullptr};
+    lay1(z);
+    HLC_CHECK(sc.reserve(1, z.off + 256));
+    Carve c{(char*)dev->sarena[1]};
+    lay1(c);
+  }
   HLC_TRY(hipMemcpyAsync(curA, offA.data(), nch * 8, hipMemcpyHostToDevice, s));
   HLC_TRY(hipMemcpyAsync(curB, offB.data(), nch * 8, hipMemcpyHostToDevice, s));
   launch_chunk_scatter(A_ra, A_dec, (uint32_t)na, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, 0.0, curA,
@@ -1827,6 +1885,12 @@ void hlc_shutdown(void) {
     if (d.cnt_host) (void)hipHostFree(d.cnt_host);
     for (auto& e : d.ev)
       if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {d.fork, d.join})
+      if (e) (void)hipEventDestroy(e);
+    if (d.side) (void)hipStreamDestroy(d.side);
+    for (void* p : d.sarena)
+      if (p) (void)hipFree(p);
+    if (d.harena) (void)hipHostFree(d.harena);
     d = Device();
   }
 }

@@ -22,7 +22,9 @@ constexpr int GROUP = 16;                             // A sources per group (on
 constexpr int MAXR = 4;                               // B ranges kept per group
 
 // Partition geometry of one call: Dec zones of height h, RA bins of width
-// 360/nbins; a source's key is (zone << rb) | bin.
+// 360/nbins; a source's key is ((zone << rb) | bin) << fb | frac, where frac
+// is the position inside the bin in units of 2^-fb bin. Keys are sorted by
+// (zone, bin) only; frac rides along and tightens the RA windows.
 struct Geom {
   double h_deg;       // zone height (deg)
   double inv_h;       // 1 / h_deg
@@ -32,6 +34,8 @@ struct Geom {
   int32_t nz;         // number of zones
   int32_t rb;         // RA bits; nbins = 1 << rb
   uint32_t nbins;
+  int32_t fb;         // RA sub-bin bits carried in the low key bits (0..8)
+  int32_t pad_;
 };
 
 // An entry count known on the host (base) plus an optional count that only
@@ -106,11 +110,24 @@ __host__ __device__ inline uint32_t bin_of(const Geom& g, double ra) {
   return (uint32_t)t;
 }
 
-__host__ __device__ inline uint32_t make_key(const Geom& g, int32_t z, uint32_t b) {
-  return ((uint32_t)z << g.rb) | b;
+// position inside bin b of an RA with bin_of(g, ra) == b, in [0, 2^fb):
+// floor((ra * scale - b) * 2^fb), so ra * scale >= b + frac / 2^fb
+__host__ __device__ inline uint32_t frac_of(const Geom& g, double ra, uint32_t b) {
+  const double t = (ra * g.bin_scale - (double)b) * (double)(1u << g.fb);
+  const double f = floor(t);
+  const double top = (double)((1u << g.fb) - 1u);
+  return f >= 0.0 ? (uint32_t)(f < top ? f : top) : 0u;
 }
-__host__ __device__ inline int32_t key_zone(const Geom& g, uint32_t k) { return (int32_t)(k >> g.rb); }
-__host__ __device__ inline uint32_t key_bin(const Geom& g, uint32_t k) { return k & (g.nbins - 1); }
+// key of (zone z, bin b) with frac 0: the smallest key of the cell
+__host__ __device__ inline uint32_t make_key(const Geom& g, int32_t z, uint32_t b) {
+  return (((uint32_t)z << g.rb) | b) << g.fb;
+}
+__host__ __device__ inline int32_t key_zone(const Geom& g, uint32_t k) { return (int32_t)(k >> (g.rb + g.fb)); }
+__host__ __device__ inline uint32_t key_bin(const Geom& g, uint32_t k) { return (k >> g.fb) & (g.nbins - 1); }
+__host__ __device__ inline uint32_t key_frac(const Geom& g, uint32_t k) { return k & ((1u << g.fb) - 1u); }
+__host__ __device__ inline bool same_zone(const Geom& g, uint32_t ka, uint32_t kb) {
+  return ((ka ^ kb) >> (g.rb + g.fb)) == 0u;
+}
 
 // ---------------------------------------------------------------------------
 // sin and cos of an angle in degrees, |x| <= 360.

@@ -11,6 +11,13 @@ namespace hlc {
 // ---- partition.hip ---------------------------------------------------------
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void launch_zero_counters(Counters* c, hipStream_t s);
+struct SortScratch {
+  uint32_t* keys_alt;
+  uint32_t* vals_alt;
+  uint32_t* counts;     // 256 * ntiles
+  uint32_t* digit_totals; // per-digit totals of one pass
+};
+
 // keys/vals for A (one entry per source, or one per source plus Dec-halo
 // copies appended after n when `halo` is set).
 // keys (and halo copies) of n sources; with src64 / src32 also each
@@ -22,27 +29,20 @@ void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, 
 void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* src, Rec32* rec, double2* radec,
                      hipStream_t s);
 
-struct SortScratch {
-  uint32_t* keys_alt;
-  uint32_t* vals_alt;
-  uint32_t* counts;     // 256 * ntiles
-  uint32_t* digit_totals; // per-digit totals of one pass
-};
 size_t sort_counts_len(uint32_t n);
 size_t sort_digit_totals_len(uint32_t n);
-// LSD radix sort of (keys, vals), ascending, stable, on key bits [0, key_bits).
-// The result ends in (keys, vals).
-// Stable LSD sort of (keys, vals) by the low key_bits bits; the result is
-// in (keys, vals). With from_alt the input is in the scratch pair instead:
-// callers that write their input there when radix_passes(key_bits) is odd
-// spare the final copy.
-int radix_passes(int key_bits);
+// Stable LSD radix sort of (keys, vals), ascending, by key bits
+// [lo_bit, key_bits) (lower bits ride along unsorted); the result is in
+// (keys, vals). With from_alt the input is in the scratch pair instead:
+// callers that write their input there when radix_passes(...) is odd spare
+// the final copy.
+int radix_passes(int key_bits, int lo_bit = 0);
 // n output pairs (and their separations, if sep) ordered by (a, b); keys,
 // vals, tmp_pairs, tmp_sep hold n entries each
 void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, uint32_t* keys, uint32_t* vals,
                 uint2* tmp_pairs, double* tmp_sep, const SortScratch& sc, hipStream_t s);
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt = false);
+                hipStream_t s, bool from_alt = false, int lo_bit = 0);
 
 void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s);
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,

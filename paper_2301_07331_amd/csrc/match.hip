@@ -230,7 +230,7 @@ __device__ inline void stage_candidates(const MatchArgs& a, const OutArgs& o, co
     const uint32_t e = b0 + lane;
     const uint2 ent = e < qn ? q[e] : make_uint2(lane, 0u);
     const ALane& A = al[ent.x & 63u];
-    const bool keep = e < qn && ((A.key ^ a.keysB[ent.y]) >> a.geom.rb) == 0u;
+    const bool keep = e < qn && same_zone(a.geom, A.key, a.keysB[ent.y]);
     const uint64_t m = __ballot(keep);
     if (m == 0) continue;
     const uint32_t leader = (uint32_t)__builtin_ctzll(m);
@@ -384,6 +384,7 @@ __global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
       uint32_t idx;
       keyA = a.keysA[cur.a_pos];
       if (a.valsA) {
+        // valsA: the entry's source index (halo bit included)
         idx = cur.va;
         if constexpr (F32) {
           const SrcRec32 r = a.srcA32[idx & IDX_MASK];

@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
       }
       const int32_t z = zone_of(g, d);
       const uint32_t b = bin_of(g, a);
-      keys[i] = make_key(g, z, b);
+      const uint32_t fr = frac_of(g, a, b);
+      keys[i] = make_key(g, z, b) | fr;
       vals[i] = i;
       if (src64 || src32) {
         double x, y, w;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
         const int32_t zl = zone_of(g, d - g.rpad_deg), zh = zone_of(g, d + g.rpad_deg);
         const int32_t other = (zl != z) ? zl : zh;
         if (other != z) {
-          hkey[j] = make_key(g, other, b);
+          hkey[j] = make_key(g, other, b) | fr;
           need |= 1u << j;
         }
       }
@@ -354,7 +355,7 @@ __global__ void k_zone_starts(const uint32_t* __restrict__ keys, DevCount nc, Ge
   uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z > (uint32_t)g.nz) return;
   if (z == (uint32_t)g.nz) { zstart[z] = n; return; }
-  zstart[z] = lower_bound_u32(keys, 0, n, (uint32_t)z << g.rb);
+  zstart[z] = lower_bound_u32(keys, 0, n, make_key(g, z, 0u));
 }
 
 // ---------------------------------------------------------------------------
@@ -611,9 +612,19 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
       // sources: bf * width is exact (width = 360 / 2^rb), bin_of is
       // monotone, and the half-width D is padded beyond every rounding, so
       // every B within r of a source of bins bf..bl lies in bins lo..hi
+      // (the sub-bin fractions of the sources in the first and last bins
+      // narrow the edges to 2^-fb bin; width and its fractions are exact)
       const double width = 360.0 / (double)nbins;
+      const double fw = width / (double)(1u << g.fb);
+      uint32_t fmin = (1u << g.fb) - 1u, fmax = 0u;
+      for (uint32_t u = q; u <= qe; ++u) {
+        const int64_t bu = key_bin(g, k[u]);
+        if (bu == bf) fmin = min(fmin, key_frac(g, k[u]));
+        if (bu == bl) fmax = max(fmax, key_frac(g, k[u]));
+      }
       const double D = zdelta[z];
-      const double x = (double)bf * width - D, y = (double)(bl + 1) * width + D;
+      const double x = (double)bf * width + (double)fmin * fw - D;
+      const double y = (double)bl * width + (double)(fmax + 1u) * fw + D;
       lo = x >= 0.0 ? (int64_t)bin_of(g, x) : (int64_t)bin_of(g, x + 360.0) - nbins;
       hi = y < 360.0 ? (int64_t)bin_of(g, y) : (int64_t)bin_of(g, y - 360.0) + nbins;
     }
@@ -622,9 +633,11 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     } else if (zs < ze) {
       auto lower = [&](uint64_t K) { return index_lower(keysB, kidx, kshift, kT, K, zs, ze); };
       uint32_t s = lower(make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)));
-      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) + 1);
+      // (the end of a cell: its last key + 1 = the first key of the next)
+      const uint64_t cell = 1ull << g.fb;
+      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) + cell);
       if (hi > nbins - 1) {  // window passes RA 360: low bins of the zone
-        uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + 1);
+        uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + cell);
         L.add(zs, e2);
       }
       L.add(s, e);
@@ -856,12 +869,12 @@ void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* sr
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
 size_t sort_digit_totals_len(uint32_t n) { (void)n; return RS_BINS; }
 
-int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
+int radix_passes(int key_bits, int lo_bit) { return (key_bits - lo_bit + 7) / 8; }
 
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt) {
+                hipStream_t s, bool from_alt, int lo_bit) {
   const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
-  const int passes = radix_passes(key_bits);
+  const int passes = radix_passes(key_bits, lo_bit);
   uint32_t *kin = keys, *vin = vals, *kout = sc.keys_alt, *vout = sc.vals_alt;
   if (from_alt) {
     std::swap(kin, kout);
@@ -870,7 +883,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bit
   if (n > 1) {
     const uint32_t ntiles = cdiv(n, RS_TILE);
     for (int p = 0; p < passes; ++p) {
-      const int shift = 8 * p;
+      const int shift = lo_bit + 8 * p;
       k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles);
       k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
       k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts,

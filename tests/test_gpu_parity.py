@@ -377,3 +377,45 @@ def test_sorted_output(hlc, prec):
                            flags=hlc.HLC_SORTED | hlc.HLC_SELF)
     assert st == hlc.HLC_OK
     check(out, sep, n, sk, sref.sep[keep], "self")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_bin_edges_and_fractions(hlc, prec):
+    """Sources exactly on, just inside and just outside RA bin edges (and at sub-bin fraction
+    edges), with partners at 0.999 r to 1.001 r across the edge: the group windows built from
+    bin edges and sub-bin fractions must keep every pair."""
+    g = synth.rng(601, 0)
+    rb = 12
+    w = 360.0 / (1 << rb)             # bin width of the tuned geometry (deg)
+    fw = w / 256.0                    # sub-bin fraction width
+    r = 2.0
+    n = 4000
+    k = g.integers(0, 1 << rb, n)
+    sub = g.integers(0, 256, n)
+    off = g.choice([0.0, 1e-13, -1e-13, 0.5 * fw, fw - 1e-12], n)
+    a_ra = np.mod(k * w + sub * fw + off, 360.0)
+    a_dec = g.uniform(-60.0, 60.0, n)
+    sgn = g.choice([-1.0, 1.0], n)
+    dist = g.uniform(0.999, 1.001, n) * r / 3600.0
+    b_ra = np.mod(a_ra + sgn * dist / np.cos(np.radians(a_dec)), 360.0)
+    b_dec = a_dec + g.normal(0.0, 1e-6, n)
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+    assert len(ref) > n // 4
+    for zh in (30.0, 600.0):
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec,
+                               tuning={"zone_height_arcsec": zh, "ra_bins_log2": rb})
+        assert_same(keys, sep, ref, label=f"zh={zh}")
+        keys, sep = gpu_xmatch(b_ra, b_dec, a_ra, a_dec, r, prec,
+                               tuning={"zone_height_arcsec": zh, "ra_bins_log2": rb})
+        ref2 = oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r)
+        assert_same(keys, sep, ref2, label=f"swapped zh={zh}")
+
+
+@pytest.mark.parametrize("items", [1, 2, 3, 5])
+def test_filter_items_per_wave(hlc, items):
+    """The filter's items-per-wave tuning changes the schedule, not the result."""
+    a_ra, a_dec, b_ra, b_dec = synth.adversarial("dense", 6000, 11, 2.0)
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, 2.0)
+    for prec in (1, 0):
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec, tuning={"filter_items": items})
+        assert_same(keys, sep, ref, label=f"items={items} prec={prec}")

@@ -27,7 +27,6 @@ namespace hlc {
 namespace {
 
 constexpr int MAX_DEVICES = 64;
-constexpr double SKY_ARCSEC2 = 5.3458e11;  // 4 pi sr in square arcsec
 constexpr double U64 = 1.1102230246251565e-16;
 constexpr double ETA64 = 4e-15;             // bound on |chord_fp64 - chord| (unit sphere)
 
@@ -37,7 +36,7 @@ struct Device {
   size_t ws_bytes = 0;
   Counters* cnt = nullptr;        // device
   Counters* cnt_host = nullptr;   // pinned host mirror
-  hipEvent_t ev[13] = {};
+  hipEvent_t ev[15] = {};
   // streaming form: device and pinned host arenas kept between calls
   // (grow-only; released by hlc_shutdown)
   void* sarena[2] = {nullptr, nullptr};
@@ -46,7 +45,9 @@ struct Device {
   size_t harena_bytes = 0;
   // A's partition runs on `side` beside B's on the caller's stream
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr;
+  // B sorted (the ranges start) and ranges done (the filter may start)
+  hipEvent_t bsorted = nullptr, prepped = nullptr;
   // staging sizes that earlier calls needed (grow-only), so a repeated
   // workload does not pay the overflow re-run again
   uint64_t hint_stage = 0, hint_cand = 0;
@@ -86,7 +87,8 @@ int get_device(Device** out, int* dev_id = nullptr) {
     HLC_TRY(hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HLC_TRY(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking));
     HLC_TRY(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
-    HLC_TRY(hipEventCreateWithFlags(&d.join, hipEventDisableTiming));
+    HLC_TRY(hipEventCreateWithFlags(&d.bsorted, hipEventDisableTiming));
+    HLC_TRY(hipEventCreateWithFlags(&d.prepped, hipEventDisableTiming));
     d.init = true;
   }
   *out = &d;
@@ -146,50 +148,136 @@ int ceil_log2(uint64_t v) {
   return b;
 }
 
+int zone_bits(int64_t nz) { return std::max(1, ceil_log2((uint64_t)nz)); }
+
 void set_radius(Geom& g, double r_arcsec) {
   g.r_deg = r_arcsec / 3600.0;
   g.rpad_deg = g.r_deg * (1.0 + 1e-9) + 1e-12;
 }
 
+// The region the zones and RA bins cover: the whole sphere, or a box around
+// the data (every valid source inside it; an RA span under 180 deg, so no
+// pair crosses the box's RA edges).
+struct Frame {
+  bool full_ra = true;
+  double dec_lo = -90.0, dec_hi = 90.0;
+  double ra_lo = 0.0, ra_span = 360.0;
+};
+
+// Smallest value >= v with at most 21 significant bits: b * (v / 2^rb) with
+// b < 2^32 is then exact in FP64.
+double round_up_21(double v) {
+  int e = 0;
+  const double m = std::frexp(v, &e);
+  return std::ldexp(std::ceil(std::ldexp(m, 20)), e - 20);
+}
+
 // Partition geometry: zone height h_as (arcsec; <= 0 = automatic from the
-// catalogue sizes), radius r (halo and windows).
-Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits) {
+// data density), radius r (halo and windows), frame f.
+Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits, const Frame& f = Frame{}) {
   Geom g;
   set_radius(g, r_arcsec);
+  const double dspan = std::max(f.dec_hi - f.dec_lo, 1e-9);
   if (!(h_as > 0)) {
-    // zone height balancing Dec and RA overhead for a uniform sky of this
-    // density: h = sqrt(GROUP / density)
-    double rho = (double)std::max<int64_t>(1, std::max(na, nb)) / SKY_ARCSEC2;
+    // zone height balancing Dec and RA overhead for a uniform density over
+    // the frame: h = sqrt(GROUP / density)
+    const double d2r = M_PI / 180.0, as_per_rad = 648000.0 / M_PI;
+    const double area_sr = std::max(std::sin(f.dec_hi * d2r) - std::sin(f.dec_lo * d2r), 1e-18) *
+                           std::max(f.ra_span * d2r, 1e-18);
+    const double rho = (double)std::max<int64_t>(1, std::max(na, nb)) / (area_sr * as_per_rad * as_per_rad);
     h_as = std::sqrt((double)GROUP / rho);
     h_as = std::min(std::max(h_as, 8.0 * r_arcsec), 3600.0);
   }
   double h = h_as / 3600.0;
   h = std::max(h, 2.0001 * g.rpad_deg);
-  h = std::max(h, 180.0 / 65536.0);
-  int64_t nz = std::max<int64_t>(1, (int64_t)std::ceil(180.0 / h));
+  h = std::max(h, dspan / 65536.0);
+  int64_t nz = std::max<int64_t>(1, (int64_t)std::ceil(dspan / h));
   g.h_deg = h;
   g.inv_h = 1.0 / h;
   g.nz = (int32_t)nz;
-  const int zb = ceil_log2((uint64_t)nz);
+  g.dec0 = f.dec_lo;
+  // at least one zone bit: the shift by rb + fb that extracts the zone must
+  // stay below 32
+  const int zb = zone_bits(nz);
   const int rb_max = std::min(30, 32 - zb);
+  const double span = f.full_ra ? 360.0 : round_up_21(std::max(f.ra_span, 1e-9));
   if (ra_bits > 0) {
     g.rb = std::min(ra_bits, rb_max);
   } else {
     // bins about h/8 wide at the equator keep the RA windows tight; the key
     // then takes every bit of the 8-bit radix digits it needs anyway
-    int need = (int)std::ceil(std::log2(360.0 * 8.0 / h));
+    int need = (int)std::ceil(std::log2(span * 8.0 / h));
     need = std::min(std::max(need, 1), rb_max);
     const int digits = (zb + need + 7) / 8;
     g.rb = std::min(8 * digits - zb, rb_max);
   }
   g.nbins = 1u << g.rb;
-  g.bin_scale = (double)g.nbins / 360.0;
+  g.full_ra = f.full_ra ? 1 : 0;
+  g.ra0 = f.full_ra ? 0.0 : f.ra_lo;
+  g.ra_width = std::ldexp(span, -g.rb);  // exact
+  g.bin_scale = (double)g.nbins / span;
   // spare low key bits carry the RA position inside the bin
   g.fb = std::min(8, std::max(0, 32 - zb - g.rb));
   return g;
 }
 
-int key_bits(const Geom& g) { return ceil_log2((uint64_t)g.nz) + g.rb + g.fb; }
+double ext_value(unsigned long long code) {
+  double v;
+  std::memcpy(&v, &code, 8);
+  return v;
+}
+
+// The frame of a call's data: a sample of both catalogues first; where its
+// box covers over a quarter of the sphere the whole sphere is the frame,
+// otherwise one pass over every source gives the exact box. (The partition
+// keys then resolve a dense patch as finely as the whole sky.)
+int data_frame(Device& dev, const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
+               const double* b_dec, int64_t nb, hipStream_t s, Frame* out) {
+  *out = Frame{};
+  Counters* hc = dev.cnt_host;
+  auto read_ext = [&]() -> int {
+    HLC_TRY(hipMemcpyAsync(hc->ext, dev.cnt->ext, sizeof(hc->ext), hipMemcpyDeviceToHost, s));
+    HLC_TRY(hipStreamSynchronize(s));
+    return HLC_OK;
+  };
+  struct Box {
+    bool any;
+    double dlo, dhi, rlo, rhi;
+  };
+  auto box = [&]() {
+    Box b;
+    b.any = hc->ext[1] != 0ull;
+    b.dlo = ext_value(~hc->ext[0]) - 90.0;
+    b.dhi = ext_value(hc->ext[1]) - 90.0;
+    b.rlo = ext_value(~hc->ext[2]);
+    b.rhi = ext_value(hc->ext[3]);
+    return b;
+  };
+  auto quarter_sky = [](const Box& b) {
+    const double d2r = M_PI / 180.0;
+    return (std::sin(b.dhi * d2r) - std::sin(b.dlo * d2r)) * (b.rhi - b.rlo) * d2r > M_PI;
+  };
+  launch_extent_sample(a_ra, a_dec, (uint32_t)na, b_ra, b_dec, (uint32_t)nb, dev.cnt, s);
+  HLC_CHECK(read_ext());
+  Box b = box();
+  if (!b.any || quarter_sky(b)) return HLC_OK;
+  launch_extent(a_ra, a_dec, (uint32_t)na, dev.cnt, s);
+  launch_extent(b_ra, b_dec, (uint32_t)nb, dev.cnt, s);
+  HLC_CHECK(read_ext());
+  b = box();
+  // a margin far above the rounding of the codes keeps every source inside
+  const double m = 1e-9;
+  out->dec_lo = std::max(-90.0, b.dlo - m);
+  out->dec_hi = std::min(90.0, b.dhi + m);
+  if (b.rhi - b.rlo < 170.0) {
+    out->full_ra = false;
+    out->ra_lo = b.rlo - m;
+    out->ra_span = (b.rhi - b.rlo) + 2.0 * m;
+  }
+  return HLC_OK;
+}
+
+int key_bits(const Geom& g) { return zone_bits(g.nz) + g.rb + g.fb; }
 
 struct Thresholds {
   double c_r, t_lo64, t_hi64, H_lo, H_hi;
@@ -268,9 +356,11 @@ void mark(Device& dev, int slot, hipStream_t s) {
 // l64 / l32: the side's records are FP64 / FP32; without a sorted layout
 // (sd.r64 / sd.r32 null) the per-source records stay in input order and the
 // kernels read them through vals
+// sorted_ev (optional) is recorded once the keys are sorted, before the
+// records are gathered.
 int partition(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
               bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd,
-              const Slots& sl, hipStream_t s) {
+              const Slots& sl, hipStream_t s, hipEvent_t sorted_ev = nullptr) {
   sd.n_src = n;
   sd.ra = ra;
   sd.dec = dec;
@@ -287,6 +377,7 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
   mark(dev, sl.sort_begin, s);
   radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, g.fb);
   mark(dev, sl.sort, s);
+  if (sorted_ev) HLC_TRY(hipEventRecord(sorted_ev, s));
   if (l64 && sd.r64) {
     if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
     else launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
@@ -399,18 +490,27 @@ OutArgs out_args(hlc_pair* pairs, double* sep, uint64_t cap, uint2* band, uint64
 // Everything after the partition: ranges, match, certification.
 void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_arcsec, bool fp32,
            bool skip_halo_a, bool self_only, const Radii& rad, const MatchWs& w,
-           hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, int filter_items, hipStream_t s) {
+           hlc_pair* out_pairs, double* out_sep, uint64_t cap, bool prof, int filter_items, hipStream_t s,
+           hipStream_t ps = nullptr) {
+  // zone tables, key index and ranges need only the sorted keys: on ps
+  // (ordered by the caller after both sorts) they overlap B's gather on s
+  if (!ps) ps = s;
   Thresholds th = thresholds(r_arcsec);
-  launch_zone_tables(g, w.zmarg, w.zdelta, s);
+  launch_zone_tables(g, w.zmarg, w.zdelta, ps);
   const uint32_t* zstart = w.zstartB;
   if (!zstart) {
-    launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, s);
+    launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, ps);
     zstart = w.zstart_buf;
   }
   const KeyIndex ki = key_index_dims(g);
-  launch_key_index(B.keys, B.cnt, ki.shift, ki.T, w.kidx, s);
-  launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, s);
-  if (prof) (void)hipEventRecord(dev.ev[8], s);
+  launch_key_index(B.keys, B.cnt, ki.shift, ki.T, w.kidx, ps);
+  launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, ps);
+  if (prof) (void)hipEventRecord(dev.ev[8], ps);
+  if (ps != s) {
+    (void)hipEventRecord(dev.prepped, ps);
+    (void)hipStreamWaitEvent(s, dev.prepped, 0);
+  }
+  if (prof) (void)hipEventRecord(dev.ev[13], s);
   MatchArgs ma{};
   ma.ranges = w.ranges;
   ma.na = A.cnt;
@@ -508,22 +608,23 @@ void fill_stats(const Counters& h, int64_t na, int64_t nb, int64_t nbh, const Ge
   g_stats.zone_height_arcsec = g.h_deg * 3600.0;
 }
 
-// Stage times from the event slots: 0 start; B partition 1-4 (keygen, sort
-// begin, sort, layout) on the call's stream; A partition 5-7 (keygen, sort,
-// layout) on the side stream from 0 on; 12 both partitions done; 8 ranges;
-// 9 filter; 10 certification and packing; 11 end. The two partitions
-// overlap, so their stage times add up to more than the wall time.
+// Stage times from the event slots: 0 start; 14 frame known; B partition
+// 1-4 (keygen, sort begin, sort, layout) on the call's stream; A partition
+// 5-7 (keygen, sort, layout) on the side stream from 14 on; 12 both sorts
+// done, 8 ranges done (side stream, beside B's layout); 13 filter start;
+// 9 filter; 10 certification and packing; 11 end. Stages on the two streams
+// overlap, so their times add up to more than the wall time.
 void fill_times(Device& dev, bool with_partition) {
   auto el = [&](int a, int b) { return (double)elapsed(dev.ev[a], dev.ev[b]); };
   if (with_partition) {
-    g_stats.t_keygen_ms = el(0, 1) + el(0, 5);
+    g_stats.t_keygen_ms = el(14, 1) + el(14, 5);
     g_stats.t_sort_ms = el(2, 3) + el(5, 6);
     g_stats.t_layout_ms = el(3, 4) + el(6, 7);
     g_stats.t_ranges_ms = el(12, 8);
   } else {
     g_stats.t_ranges_ms = el(0, 8);
   }
-  g_stats.t_match_ms = el(8, 9);
+  g_stats.t_match_ms = el(13, 9);
   g_stats.t_certify_ms = el(9, 10);
   g_stats.t_total_ms = el(0, 11);
 }
@@ -546,7 +647,10 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   const bool prof = (o->flags & HLC_PROFILE) != 0;
   const bool fp32 = o->precision == HLC_FP32_RECHECK;
   const bool self = (o->flags & HLC_SELF) != 0;
-  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o));
+  if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
+  Frame f;
+  HLC_CHECK(data_frame(*dev, a_ra, a_dec, self ? 0 : na, b_ra, b_dec, nb, s, &f));
+  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
   const uint32_t nB = (uint32_t)nb;
   // self-match: A's entries are B's (halo copies included)
   const uint32_t nA = self ? 2 * nB : (uint32_t)na;
@@ -570,29 +674,28 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   Carve c{(char*)dev->ws};
   lay(c);
 
-  if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
+  if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
   launch_zero_counters(dev->cnt, s);
-  // A's partition on the side stream, B's on the caller's; they meet before
-  // the ranges (separate sort scratch, disjoint counter fields)
+  // A's partition on the side stream, B's on the caller's; the ranges run on
+  // the side stream once both are sorted, beside B's gather (separate sort
+  // scratch, disjoint counter fields)
   const Slots slB = prof ? Slots{1, 2, 3, 4} : NO_SLOTS;
   const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
   if (!self) {
     HLC_TRY(hipEventRecord(dev->fork, s));
     HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
     HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side));
-    HLC_TRY(hipEventRecord(dev->join, dev->side));
   }
-  HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s));
+  HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s, dev->bsorted));
   if (self) {
     // one partition serves both roles; its halo copies are skipped as A
     for (int k : {slA.keygen, slA.sort, slA.layout}) mark(*dev, k, s);
     A = B;
-  } else {
-    HLC_TRY(hipStreamWaitEvent(s, dev->join, 0));
   }
-  mark(*dev, prof ? 12 : -1, s);
+  HLC_TRY(hipStreamWaitEvent(dev->side, dev->bsorted, 0));
+  mark(*dev, prof ? 12 : -1, dev->side);
   match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, w, out_pairs,
-        (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, tuned_items(o), s);
+        (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, tuned_items(o), s, dev->side);
   HLC_CHECK(read_counters(*dev, s, prof));
 
   const Counters& h = *dev->cnt_host;
@@ -1885,7 +1988,7 @@ void hlc_shutdown(void) {
     if (d.cnt_host) (void)hipHostFree(d.cnt_host);
     for (auto& e : d.ev)
       if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {d.fork, d.join})
+    for (hipEvent_t e : {d.fork, d.bsorted, d.prepped})
       if (e) (void)hipEventDestroy(e);
     if (d.side) (void)hipStreamDestroy(d.side);
     for (void* p : d.sarena)

@@ -389,18 +389,9 @@ __global__ __launch_bounds__(256) void k_batch_ranges(const uint32_t* __restrict
   }
   const uint32_t p0 = grp * GROUP;
   const uint32_t cnt = min((uint32_t)GROUP, na - p0);
-  uint32_t s_[3 * GROUP], e_[3 * GROUP];
-  int n = 0;
-  auto add = [&](uint32_t a, uint32_t b) {
-    if (a >= b) return;
-    if (n > 0 && a <= e_[n - 1]) {
-      if (b > e_[n - 1]) e_[n - 1] = b;
-      return;
-    }
-    s_[n] = a;
-    e_[n] = b;
-    ++n;
-  };
+  RangeList L;
+  L.clear();
+  auto add = [&](uint32_t a, uint32_t b) { L.add(a, b); };
   uint32_t q = 0;
   while (q < cnt) {
     const uint32_t k0 = keysA[p0 + q];
@@ -436,26 +427,14 @@ __global__ __launch_bounds__(256) void k_batch_ranges(const uint32_t* __restrict
     }
     q = qe + 1;
   }
-  while (n > MAXR) {
-    int best = 0;
-    uint32_t gap = 0xffffffffu;
-    for (int t = 0; t + 1 < n; ++t) {
-      uint32_t gp = s_[t + 1] - e_[t];
-      if (gp < gap) { gap = gp; best = t; }
-    }
-    e_[best] = e_[best + 1];
-    for (int t = best + 1; t + 1 < n; ++t) {
-      s_[t] = s_[t + 1];
-      e_[t] = e_[t + 1];
-    }
-    --n;
-  }
   GroupRanges R;
   uint32_t work = 0;
+  const int n = L.n;
+#pragma unroll
   for (int t = 0; t < MAXR; ++t) {
-    R.start[t] = t < n ? s_[t] : 0u;
-    R.end[t] = t < n ? e_[t] : 0u;
-    if (t < n) work += e_[t] - s_[t];
+    R.start[t] = t < n ? L.s[t] : 0u;
+    R.end[t] = t < n ? L.e[t] : 0u;
+    if (t < n) work += L.e[t] - L.s[t];
   }
   R.count = (uint32_t)n;
   R.pad_[0] = R.pad_[1] = R.pad_[2] = 0u;

@@ -21,21 +21,27 @@ constexpr uint32_t IDX_MASK = 0x7fffffffu;
 constexpr int GROUP = 16;                             // A sources per group (one DPP row)
 constexpr int MAXR = 4;                               // B ranges kept per group
 
-// Partition geometry of one call: Dec zones of height h, RA bins of width
-// 360/nbins; a source's key is ((zone << rb) | bin) << fb | frac, where frac
-// is the position inside the bin in units of 2^-fb bin. Keys are sorted by
-// (zone, bin) only; frac rides along and tightens the RA windows.
+// Partition geometry of one call: Dec zones of height h from dec0, RA bins
+// of width ra_width from ra0 (the frame spans the data's footprint, or the
+// whole sphere: dec0 = -90, ra0 = 0, nbins * ra_width = 360, full_ra); a
+// source's key is ((zone << rb) | bin) << fb | frac, where frac is the
+// position inside the bin in units of 2^-fb bin. Keys are sorted by (zone,
+// bin) only; frac rides along and tightens the RA windows. Sources outside
+// the frame are clamped into its edge cells (monotone, so still correct).
 struct Geom {
   double h_deg;       // zone height (deg)
   double inv_h;       // 1 / h_deg
-  double bin_scale;   // nbins / 360
+  double bin_scale;   // 1 / ra_width
+  double dec0;        // Dec of the lower edge of zone 0
+  double ra0;         // RA of the lower edge of bin 0
+  double ra_width;    // bin width (deg)
   double r_deg;       // r_arcsec / 3600
   double rpad_deg;    // r padded outward for windows and halos
   int32_t nz;         // number of zones
   int32_t rb;         // RA bits; nbins = 1 << rb
   uint32_t nbins;
   int32_t fb;         // RA sub-bin bits carried in the low key bits (0..8)
-  int32_t pad_;
+  int32_t full_ra;    // the bins cover RA [0, 360): windows wrap at the seam
 };
 
 // An entry count known on the host (base) plus an optional count that only
@@ -72,6 +78,9 @@ struct Counters {
   unsigned long long aux[2];      // entry counts of multi-entry keygens (A, B)
   unsigned long long region_max;  // largest pair-region fill (compaction)
   unsigned long long cand_max;    // largest candidate-region fill
+  // data footprint, each as a max of order-preserving codes of non-negative
+  // doubles: ~code(dec + 90), code(dec + 90), ~code(ra), code(ra)
+  unsigned long long ext[4];
 };
 
 struct Rec64 {      // FP64 working record (32 B)
@@ -97,23 +106,23 @@ __host__ __device__ inline bool valid_pos(double ra, double dec) {
 }
 
 __host__ __device__ inline int32_t zone_of(const Geom& g, double dec) {
-  double t = floor((dec + 90.0) * g.inv_h);
+  double t = floor((dec - g.dec0) * g.inv_h);
   if (!(t >= 0.0)) return 0;
   if (t > (double)(g.nz - 1)) return g.nz - 1;
   return (int32_t)t;
 }
 
 __host__ __device__ inline uint32_t bin_of(const Geom& g, double ra) {
-  double t = floor(ra * g.bin_scale);
+  double t = floor((ra - g.ra0) * g.bin_scale);
   if (!(t >= 0.0)) return 0u;
   if (t > (double)(g.nbins - 1)) return g.nbins - 1;
   return (uint32_t)t;
 }
 
 // position inside bin b of an RA with bin_of(g, ra) == b, in [0, 2^fb):
-// floor((ra * scale - b) * 2^fb), so ra * scale >= b + frac / 2^fb
+// floor(((ra - ra0) * scale - b) * 2^fb), so (ra - ra0) * scale >= b + frac / 2^fb
 __host__ __device__ inline uint32_t frac_of(const Geom& g, double ra, uint32_t b) {
-  const double t = (ra * g.bin_scale - (double)b) * (double)(1u << g.fb);
+  const double t = ((ra - g.ra0) * g.bin_scale - (double)b) * (double)(1u << g.fb);
   const double f = floor(t);
   const double top = (double)((1u << g.fb) - 1u);
   return f >= 0.0 ? (uint32_t)(f < top ? f : top) : 0u;
@@ -385,14 +394,70 @@ __device__ inline uint32_t rank_in(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// At most MAXR ascending B ranges, kept in registers (every index below is
+// static): a range touching or overlapping the last one extends it; one
+// more than MAXR is merged across the smallest gap. Merging only adds B
+// entries of the window's neighbourhood (other-zone entries are dropped by
+// the filter), so the ranges still cover every candidate.
+struct RangeList {
+  uint32_t s[MAXR + 1];
+  uint32_t e[MAXR + 1];
+  int n;
+  __device__ void clear() {
+    n = 0;
+#pragma unroll
+    for (int i = 0; i <= MAXR; ++i) s[i] = e[i] = 0u;
+  }
+  __device__ void add(uint32_t a, uint32_t b) {
+    if (a >= b) return;
+    bool merged = false;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i)
+      if (i == n - 1 && a <= e[i]) {  // overlapping or touching the previous one
+        e[i] = max(e[i], b);
+        merged = true;
+      }
+    if (merged) return;
+#pragma unroll
+    for (int i = 0; i <= MAXR; ++i)
+      if (i == n) {
+        s[i] = a;
+        e[i] = b;
+      }
+    ++n;
+    if (n <= MAXR) return;
+    int best = 0;
+    uint32_t gap = s[1] - e[0];
+#pragma unroll
+    for (int i = 1; i < MAXR; ++i)
+      if (s[i + 1] - e[i] < gap) {
+        gap = s[i + 1] - e[i];
+        best = i;
+      }
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      if (i == best) e[i] = e[i + 1];
+      if (i > best) {
+        s[i] = s[i + 1];
+        e[i] = e[i + 1];
+      }
+    }
+    n = MAXR;
+  }
+};
+
 // Broadcast lane n of each 16-lane row to the whole row (DPP row_newbcast).
+// Every lane has a valid source, so the zero "old" value is never seen; it
+// lets the compiler fold the broadcast into the VALU op that consumes it
+// (v_sub_f32_dpp instead of v_mov_b32_dpp + v_sub_f32).
 template <int N>
 __device__ inline float row_bcast(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + N, 0xf, 0xf, false));
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + N, 0xf, 0xf, true));
 }
 template <int N>
 __device__ inline uint32_t row_bcast_u(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + N, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + N, 0xf, 0xf, true);
 }
 template <int N>
 __device__ inline double row_bcast(double v) {

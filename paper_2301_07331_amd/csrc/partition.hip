@@ -107,12 +107,28 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
   uint32_t hkey[KG_ITEMS];
   uint32_t need = 0;  // bit j: item j has a halo copy
   bool bad = false;
+  // every load of the tile in flight before the first use
+  double av[KG_ITEMS], dv[KG_ITEMS];
+  if (base + KG_TILE <= n) {
+#pragma unroll
+    for (int j = 0; j < KG_ITEMS; ++j) {
+      av[j] = ra[base + (uint32_t)j * 256u + t];
+      dv[j] = dec[base + (uint32_t)j * 256u + t];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KG_ITEMS; ++j) {
+      const uint32_t i = base + (uint32_t)j * 256u + t;
+      av[j] = i < n ? ra[i] : 0.0;
+      dv[j] = i < n ? dec[i] : 0.0;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < KG_ITEMS; ++j) {
     const uint32_t i = base + (uint32_t)j * 256u + t;
     hkey[j] = 0u;
     if (i < n) {
-      double a = ra[i], d = dec[i];
+      double a = av[j], d = dv[j];
       const bool ok = valid_pos(a, d);
       if (!ok) {
         bad = true;
@@ -190,11 +206,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
   for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&h[0][0])[k] = 0u;
   __syncthreads();
   const uint32_t base = blockIdx.x * RS_TILE;
+  // every load in flight before the first use
+  uint32_t k[RS_ITEMS];
+  if (base + RS_TILE <= n) {
 #pragma unroll
-  for (int j = 0; j < RS_ITEMS; ++j) {
-    uint32_t e = base + j * RS_THREADS + t;
-    if (e < n) atomicAdd(&h[w][(keys[e] >> shift) & 0xffu], 1u);
+    for (int j = 0; j < RS_ITEMS; ++j) k[j] = keys[base + j * RS_THREADS + t];
+  } else {
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+      const uint32_t e = base + j * RS_THREADS + t;
+      k[j] = e < n ? keys[e] : 0u;
+    }
   }
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j)
+    if (base + j * RS_THREADS + t < n) atomicAdd(&h[w][(k[j] >> shift) & 0xffu], 1u);
   __syncthreads();
   counts[t * ntiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
@@ -243,20 +269,27 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   }
   __syncthreads();
 
-  // wave w owns tile elements [w*1024, (w+1)*1024), 64 per round
+  // wave w owns tile elements [w*1024, (w+1)*1024), 64 per round; every
+  // load in flight before the first use
   uint32_t key[RS_ITEMS], val[RS_ITEMS];
+  const uint32_t e0 = base + w * (RS_TILE / 4) + lane;
+  if (tile_n == (uint32_t)RS_TILE) {
 #pragma unroll
-  for (int j = 0; j < RS_ITEMS; ++j) {
-    uint32_t e = base + w * (RS_TILE / 4) + j * 64 + lane;
-    if (e < n) {
-      key[j] = keys_in[e];
-      val[j] = vals_in[e];
-      atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
-    } else {
-      key[j] = 0u;
-      val[j] = 0u;
+    for (int j = 0; j < RS_ITEMS; ++j) {
+      key[j] = keys_in[e0 + j * 64];
+      val[j] = vals_in[e0 + j * 64];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+      const uint32_t e = e0 + j * 64;
+      key[j] = e < n ? keys_in[e] : 0u;
+      val[j] = e < n ? vals_in[e] : 0u;
     }
   }
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j)
+    if (e0 + j * 64 < n) atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
   __syncthreads();
   {
     const uint32_t d = t;
@@ -311,7 +344,7 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double* __res
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (uint32_t)g.nz) {
     const int32_t z = (int32_t)i;
-    double lo = -90.0 + (double)z * g.h_deg;
+    double lo = g.dec0 + (double)z * g.h_deg;
     double hi = lo + g.h_deg;
     // largest |Dec| a source assigned to this zone can have (padded for the
     // rounding of the zone formula)
@@ -564,22 +597,9 @@ __device__ inline uint32_t index_lower(const uint32_t* keys, const uint32_t* idx
   return l;
 }
 
-struct RangeList {
-  uint32_t s[3 * GROUP];
-  uint32_t e[3 * GROUP];
-  int n;
-  __device__ void add(uint32_t a, uint32_t b) {
-    if (a >= b) return;
-    if (n > 0 && a <= e[n - 1]) {  // overlapping or touching the previous one
-      if (b > e[n - 1]) e[n - 1] = b;
-      return;
-    }
-    s[n] = a;
-    e[n] = b;
-    ++n;
-  }
-};
-
+// One thread per group of GROUP consecutive sorted A entries; the group's
+// keys are staged in LDS (a per-thread row, read with runtime indices).
+constexpr int RG_STRIDE = GROUP + 1;  // padded row: no LDS bank conflicts
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keysA, DevCount nac,
                                                 const uint32_t* __restrict__ kidx, int kshift, uint32_t kT,
                                                 const uint32_t* __restrict__ keysB,
@@ -587,16 +607,32 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
                                                 const int32_t* __restrict__ zmarg,
                                                 const double* __restrict__ zdelta, Geom g,
                                                 GroupRanges* __restrict__ out) {
+  __shared__ uint32_t s_keys[256 * RG_STRIDE];
   const uint32_t na = nac.get();
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
   if (grp >= ngroups) return;
   const uint32_t p0 = grp * GROUP;
   const uint32_t cnt = min((uint32_t)GROUP, na - p0);
-  uint32_t k[GROUP];
-  for (uint32_t q = 0; q < cnt; ++q) k[q] = keysA[p0 + q];
+  uint32_t* k = s_keys + threadIdx.x * RG_STRIDE;  // this thread's row only
+  if (cnt == (uint32_t)GROUP) {
+    // the group's keys in four 16-B loads (p0 is a multiple of 16)
+    const uint4* k4 = reinterpret_cast<const uint4*>(keysA + p0);
+    uint4 v[GROUP / 4];
+#pragma unroll
+    for (int r = 0; r < GROUP / 4; ++r) v[r] = k4[r];
+#pragma unroll
+    for (int r = 0; r < GROUP / 4; ++r) {
+      k[4 * r] = v[r].x;
+      k[4 * r + 1] = v[r].y;
+      k[4 * r + 2] = v[r].z;
+      k[4 * r + 3] = v[r].w;
+    }
+  } else {
+    for (uint32_t q = 0; q < cnt; ++q) k[q] = keysA[p0 + q];
+  }
   RangeList L;
-  L.n = 0;
+  L.clear();
   const int64_t nbins = g.nbins;
   uint32_t q = 0;
   while (q < cnt) {
@@ -614,7 +650,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
       // every B within r of a source of bins bf..bl lies in bins lo..hi
       // (the sub-bin fractions of the sources in the first and last bins
       // narrow the edges to 2^-fb bin; width and its fractions are exact)
-      const double width = 360.0 / (double)nbins;
+      const double width = g.ra_width;
       const double fw = width / (double)(1u << g.fb);
       uint32_t fmin = (1u << g.fb) - 1u, fmax = 0u;
       for (uint32_t u = q; u <= qe; ++u) {
@@ -623,10 +659,17 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
         if (bu == bl) fmax = max(fmax, key_frac(g, k[u]));
       }
       const double D = zdelta[z];
-      const double x = (double)bf * width + (double)fmin * fw - D;
-      const double y = (double)bl * width + (double)(fmax + 1u) * fw + D;
-      lo = x >= 0.0 ? (int64_t)bin_of(g, x) : (int64_t)bin_of(g, x + 360.0) - nbins;
-      hi = y < 360.0 ? (int64_t)bin_of(g, y) : (int64_t)bin_of(g, y - 360.0) + nbins;
+      const double x = g.ra0 + ((double)bf * width + (double)fmin * fw) - D;
+      const double y = g.ra0 + ((double)bl * width + (double)(fmax + 1u) * fw) + D;
+      if (g.full_ra) {
+        lo = x >= 0.0 ? (int64_t)bin_of(g, x) : (int64_t)bin_of(g, x + 360.0) - nbins;
+        hi = y < 360.0 ? (int64_t)bin_of(g, y) : (int64_t)bin_of(g, y - 360.0) + nbins;
+      } else {
+        // a partial frame holds every source and spans less than 180 deg
+        // of RA, so no pair crosses its RA edges: clamp, never wrap
+        lo = (int64_t)bin_of(g, x);
+        hi = (int64_t)bin_of(g, y);
+      }
     }
     if (m < 0 || hi - lo + 1 >= nbins) {
       L.add(zs, ze);
@@ -648,22 +691,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     }
     q = qe + 1;
   }
-  // keep at most MAXR ranges by merging across the smallest gaps
-  while (L.n > MAXR) {
-    int best = 0;
-    uint32_t gap = 0xffffffffu;
-    for (int t = 0; t + 1 < L.n; ++t) {
-      uint32_t gp = L.s[t + 1] - L.e[t];
-      if (gp < gap) { gap = gp; best = t; }
-    }
-    L.e[best] = L.e[best + 1];
-    for (int t = best + 1; t + 1 < L.n; ++t) {
-      L.s[t] = L.s[t + 1];
-      L.e[t] = L.e[t + 1];
-    }
-    --L.n;
-  }
   GroupRanges R;
+#pragma unroll
   for (int t = 0; t < MAXR; ++t) {
     R.start[t] = t < L.n ? L.s[t] : 0u;
     R.end[t] = t < L.n ? L.e[t] : 0u;
@@ -745,7 +774,7 @@ __global__ __launch_bounds__(256) void k_equal_ranges(const uint32_t* __restrict
   if (grp >= ngroups) return;
   const uint32_t p0 = grp * GROUP, cnt = min((uint32_t)GROUP, na - p0);
   RangeList L;
-  L.n = 0;
+  L.clear();
   uint32_t q = 0;
   while (q < cnt) {
     const uint32_t k = keysA[p0 + q];
@@ -756,21 +785,8 @@ __global__ __launch_bounds__(256) void k_equal_ranges(const uint32_t* __restrict
     L.add(s, e);
     q = qe + 1;
   }
-  while (L.n > MAXR) {
-    int best = 0;
-    uint32_t gap = 0xffffffffu;
-    for (int t = 0; t + 1 < L.n; ++t) {
-      const uint32_t gp = L.s[t + 1] - L.e[t];
-      if (gp < gap) { gap = gp; best = t; }
-    }
-    L.e[best] = L.e[best + 1];
-    for (int t = best + 1; t + 1 < L.n; ++t) {
-      L.s[t] = L.s[t + 1];
-      L.e[t] = L.e[t + 1];
-    }
-    --L.n;
-  }
   GroupRanges R;
+#pragma unroll
   for (int t = 0; t < MAXR; ++t) {
     R.start[t] = t < L.n ? L.s[t] : 0u;
     R.end[t] = t < L.n ? L.e[t] : 0u;
@@ -807,6 +823,82 @@ __global__ void k_pairs_permute(const uint2* __restrict__ p, const double* __res
     tp[i] = p[j];
     if (sep) ts[i] = sep[j];
   }
+}
+
+// ---------------------------------------------------------------------------
+// data footprint (Dec and RA extent of valid sources) for the geometry frame
+// ---------------------------------------------------------------------------
+__device__ inline unsigned long long ord_code(double v) {  // v >= 0
+  return (unsigned long long)__double_as_longlong(v);
+}
+
+__device__ inline void ext_reduce(unsigned long long e[4], Counters* cnt, bool block_level) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int d = 32; d > 0; d >>= 1) {
+      const unsigned long long o = __shfl_xor(e[k], d);
+      e[k] = o > e[k] ? o : e[k];
+    }
+  __shared__ unsigned long long s_e[16][4];  // up to 16 waves
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0)
+    for (int k = 0; k < 4; ++k) s_e[w][k] = e[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long m = 0ull;
+    for (uint32_t u = 0; u < (blockDim.x >> 6); ++u) m = s_e[u][threadIdx.x] > m ? s_e[u][threadIdx.x] : m;
+    if (block_level) atomicMax(&cnt->ext[threadIdx.x], m);
+    else cnt->ext[threadIdx.x] = m;
+  }
+}
+
+__device__ inline void ext_add(unsigned long long e[4], double a, double d) {
+  if (!valid_pos(a, d)) return;
+  const unsigned long long cd = ord_code(d + 90.0), ca = ord_code(a);
+  e[0] = ~cd > e[0] ? ~cd : e[0];
+  e[1] = cd > e[1] ? cd : e[1];
+  e[2] = ~ca > e[2] ? ~ca : e[2];
+  e[3] = ca > e[3] ? ca : e[3];
+}
+
+// One block of 1024 threads: a sample of up to 2 x 4096 sources, 64 runs
+// of 64 consecutive sources per catalogue, evenly spaced (few pages, so few
+// address translations); every load is issued before the first use.
+__device__ inline uint32_t sample_index(uint32_t run, uint32_t lane, uint32_t n) {
+  if (n <= 64u) return lane % n;
+  const uint32_t start = (uint32_t)(((uint64_t)run * n) / 64u);
+  return min(start, n - 64u) + lane;
+}
+
+__global__ __launch_bounds__(1024) void k_extent_sample(const double* __restrict__ ra1,
+                                                        const double* __restrict__ dec1, uint32_t n1,
+                                                        const double* __restrict__ ra2,
+                                                        const double* __restrict__ dec2, uint32_t n2, Counters* cnt) {
+  constexpr int PER = 4;  // runs per wave and catalogue (16 waves x 4 = 64 runs)
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  double a[2 * PER], d[2 * PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const uint32_t run = w + 16u * (uint32_t)j;
+    const uint32_t i1 = n1 ? sample_index(run, lane, n1) : 0u, i2 = n2 ? sample_index(run, lane, n2) : 0u;
+    a[j] = n1 ? ra1[i1] : -1.0;
+    d[j] = n1 ? dec1[i1] : 0.0;
+    a[PER + j] = n2 ? ra2[i2] : -1.0;
+    d[PER + j] = n2 ? dec2[i2] : 0.0;
+  }
+  unsigned long long e[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+  for (int j = 0; j < 2 * PER; ++j) ext_add(e, a[j], d[j]);
+  ext_reduce(e, cnt, false);
+}
+
+// Every source; one atomic per value and block.
+__global__ __launch_bounds__(256) void k_extent(const double* __restrict__ ra, const double* __restrict__ dec,
+                                                uint32_t n, Counters* cnt) {
+  unsigned long long e[4] = {0ull, 0ull, 0ull, 0ull};
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    ext_add(e, ra[i], dec[i]);
+  ext_reduce(e, cnt, true);
 }
 
 }  // namespace
@@ -907,6 +999,16 @@ void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, u
   k_pairs_permute<<<cdiv(n, 256), 256, 0, s>>>(pairs, sep, vals, n, tmp_pairs, tmp_sep);
   (void)hipMemcpyAsync(pairs, tmp_pairs, (size_t)n * sizeof(uint2), hipMemcpyDeviceToDevice, s);
   if (sep) (void)hipMemcpyAsync(sep, tmp_sep, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+void launch_extent_sample(const double* ra1, const double* dec1, uint32_t n1, const double* ra2, const double* dec2,
+                          uint32_t n2, Counters* cnt, hipStream_t s) {
+  k_extent_sample<<<1, 1024, 0, s>>>(ra1, dec1, n1, ra2, dec2, n2, cnt);
+}
+
+void launch_extent(const double* ra, const double* dec, uint32_t n, Counters* cnt, hipStream_t s) {
+  if (n == 0) return;
+  k_extent<<<std::min<uint32_t>(1024, cdiv(n, 256 * 64)), 256, 0, s>>>(ra, dec, n, cnt);
 }
 
 void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s) {

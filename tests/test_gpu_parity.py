@@ -419,3 +419,54 @@ def test_filter_items_per_wave(hlc, items):
     for prec in (1, 0):
         keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec, tuning={"filter_items": items})
         assert_same(keys, sep, ref, label=f"items={items} prec={prec}")
+
+
+def _framed_cases():
+    """Footprints for the data-framed partition: a dense patch (partial RA frame), a polar
+    sector under 170 deg of RA with pairs across the pole, a thin equatorial ring (whole RA,
+    Dec framed) with pairs across RA 0/360, a 169.9-deg RA band, and a dense patch with a
+    few far outliers that a sample of the catalogues misses."""
+    g = synth.rng(602, 0)
+    ARC = 1.0 / 3600.0
+    out = []
+    a = synth.uniform_patch(g, 20000, 150.0, 150.2, 10.0, 10.2)
+    b = synth.gaussian_offset(g, a[0][:8000], a[1][:8000], 0.7 * ARC)
+    out.append(("dense patch", a[0], a[1], b[0], b[1], 1.0))
+    ra = g.uniform(10.0, 175.0, 3000)
+    dec = 90.0 - g.uniform(0.0, 30.0 * ARC, 3000)
+    ra2 = g.uniform(10.0, 175.0, 3000)
+    dec2 = 90.0 - g.uniform(0.0, 30.0 * ARC, 3000)
+    out.append(("polar sector", ra, dec, ra2, dec2, 5.0))
+    ra = synth._wrap_ra(g.uniform(0.0, 360.0, 30000))
+    dec = g.uniform(-0.01, 0.01, 30000)
+    rb_, db_ = synth.gaussian_offset(g, ra[:15000], dec[:15000], 1.0 * ARC)
+    ra[:50] = synth._wrap_ra(g.uniform(-1e-4, 1e-4, 50))
+    rb_[:50] = synth._wrap_ra(ra[:50] + g.uniform(-5e-4, 5e-4, 50))
+    db_[:50] = dec[:50] + g.uniform(-5e-4, 5e-4, 50)
+    out.append(("equatorial ring", ra, dec, rb_, db_, 2.0))
+    a = synth.uniform_patch(g, 20000, 100.0, 269.9, -0.2, 0.2)
+    b = synth.gaussian_offset(g, a[0][:10000], a[1][:10000], 20.0 * ARC)
+    out.append(("169.9-deg band", a[0], a[1], b[0], b[1], 30.0))
+    a_ra, a_dec = synth.uniform_patch(g, 200000, 150.0, 150.5, 10.0, 10.5)
+    b_ra, b_dec = synth.gaussian_offset(g, a_ra[:50000], a_dec[:50000], 0.5 * ARC)
+    a_ra[7:10] = [200.0, 210.0, 150.25]
+    a_dec[7:10] = [-60.0, 45.0, -89.9999]
+    b_ra[11:14] = a_ra[7:10] + 1e-5
+    b_dec[11:14] = a_dec[7:10] + 1e-4 * ARC
+    out.append(("patch with outliers", a_ra, a_dec, b_ra, b_dec, 1.0))
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_framed_geometry(hlc, prec):
+    """Zones and RA bins span the data's footprint (frame edges, partial RA frames, poles)."""
+    for name, a_ra, a_dec, b_ra, b_dec, r in _framed_cases():
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        assert len(ref) > 0, name
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec)
+        assert_same(keys, sep, ref, label=name)
+        st = hlc.last_stats()
+        _print(name, len(ref), "zones", st["n_zones"], "ra_bits", st["ra_bits"],
+               "h", round(st["zone_height_arcsec"], 3))
+        keys, sep = gpu_xmatch(b_ra, b_dec, a_ra, a_dec, r, prec)
+        assert_same(keys, sep, oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r), label=name + " swapped")

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 #include <new>
 #include <string>
@@ -52,6 +53,12 @@ struct Device {
   // workload does not pay the overflow re-run again
   uint64_t hint_stage = 0, hint_cand = 0;
   int ncu = 0;  // compute units (persistent grids)
+  bool last_full = true;  // the last call's frame was the whole sphere
+  // the footprint sample's result, written by the kernel into mapped host
+  // memory (4 values, then the call's sequence number) and polled
+  unsigned long long* fmsg_host = nullptr;
+  unsigned long long* fmsg_dev = nullptr;
+  unsigned long long fseq = 0;
 };
 
 Device g_dev[MAX_DEVICES];
@@ -89,6 +96,9 @@ int get_device(Device** out, int* dev_id = nullptr) {
     HLC_TRY(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
     HLC_TRY(hipEventCreateWithFlags(&d.bsorted, hipEventDisableTiming));
     HLC_TRY(hipEventCreateWithFlags(&d.prepped, hipEventDisableTiming));
+    HLC_TRY(hipHostMalloc(&d.fmsg_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(d.fmsg_host, 0, 64);
+    HLC_TRY(hipHostGetDevicePointer((void**)&d.fmsg_dev, d.fmsg_host, 0));
     d.init = true;
   }
   *out = &d;
@@ -231,8 +241,19 @@ double ext_value(unsigned long long code) {
 // box covers over a quarter of the sphere the whole sphere is the frame,
 // otherwise one pass over every source gives the exact box. (The partition
 // keys then resolve a dense patch as finely as the whole sky.)
-int data_frame(Device& dev, const double* a_ra, const double* a_dec, int64_t na, const double* b_ra,
-               const double* b_dec, int64_t nb, hipStream_t s, Frame* out) {
+// Launches the footprint sample of a call; returns its sequence number for
+// frame_finish.
+unsigned long long frame_sample(Device& dev, const double* a_ra, const double* a_dec, int64_t na,
+                                const double* b_ra, const double* b_dec, int64_t nb, hipStream_t s) {
+  const unsigned long long seq = ++dev.fseq;
+  launch_extent_sample(a_ra, a_dec, (uint32_t)na, b_ra, b_dec, (uint32_t)nb, dev.cnt, dev.fmsg_dev, seq, s);
+  return seq;
+}
+
+bool is_full(const Frame& f) { return f.full_ra && f.dec_lo == -90.0 && f.dec_hi == 90.0; }
+
+int frame_finish(Device& dev, unsigned long long seq, const double* a_ra, const double* a_dec, int64_t na,
+                 const double* b_ra, const double* b_dec, int64_t nb, hipStream_t s, Frame* out) {
   *out = Frame{};
   Counters* hc = dev.cnt_host;
   auto read_ext = [&]() -> int {
@@ -257,8 +278,20 @@ int data_frame(Device& dev, const double* a_ra, const double* a_dec, int64_t na,
     const double d2r = M_PI / 180.0;
     return (std::sin(b.dhi * d2r) - std::sin(b.dlo * d2r)) * (b.rhi - b.rlo) * d2r > M_PI;
   };
-  launch_extent_sample(a_ra, a_dec, (uint32_t)na, b_ra, b_dec, (uint32_t)nb, dev.cnt, s);
-  HLC_CHECK(read_ext());
+  // the sample's result is polled in host memory (no stream round trip); a
+  // result that does not show up falls back to a stream synchronisation
+  {
+    volatile unsigned long long* msg = dev.fmsg_host;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (__atomic_load_n(&dev.fmsg_host[4], __ATOMIC_ACQUIRE) != seq) {
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+        HLC_TRY(hipStreamSynchronize(s));
+        HLC_TRY(hipGetLastError());
+        if (__atomic_load_n(&dev.fmsg_host[4], __ATOMIC_ACQUIRE) != seq) return HLC_E_DEVICE;
+      }
+    }
+    for (int k = 0; k < 4; ++k) hc->ext[k] = msg[k];
+  }
   Box b = box();
   if (!b.any || quarter_sky(b)) return HLC_OK;
   launch_extent(a_ra, a_dec, (uint32_t)na, dev.cnt, s);
@@ -356,17 +389,18 @@ void mark(Device& dev, int slot, hipStream_t s) {
 // l64 / l32: the side's records are FP64 / FP32; without a sorted layout
 // (sd.r64 / sd.r32 null) the per-source records stay in input order and the
 // kernels read them through vals
-// sorted_ev (optional) is recorded once the keys are sorted, before the
-// records are gathered.
-int partition(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
-              bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd,
-              const Slots& sl, hipStream_t s, hipEvent_t sorted_ev = nullptr) {
+// Partition of one side in two steps (the keygen can run on another stream
+// than the sort): keys (and the per-source records) first, then the sort and
+// the sorted layout. sorted_ev (optional) is recorded once the keys are
+// sorted, before the records are gathered.
+void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
+                    bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd, const Slots& sl,
+                    hipStream_t s) {
   sd.n_src = n;
   sd.ra = ra;
   sd.dec = dec;
   // an odd number of radix passes ends in the scratch pair unless it starts there
-  const int bits = key_bits(g);
-  const bool from_alt = (radix_passes(bits, g.fb) & 1) != 0;
+  const bool from_alt = (radix_passes(key_bits(g), g.fb) & 1) != 0;
   uint32_t* kk = from_alt ? sc.keys_alt : sd.keys;
   uint32_t* vv = from_alt ? sc.vals_alt : sd.vals;
   launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
@@ -374,20 +408,33 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
   mark(dev, sl.keygen, s);
   sd.n_cap = halo ? 2 * n : n;
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
+}
+
+int partition_sort(Device& dev, const Geom& g, bool l64, bool l32, const SortScratch& sc, Side& sd,
+                   const Slots& sl, hipStream_t s, hipEvent_t sorted_ev = nullptr) {
+  const int bits = key_bits(g);
+  const bool from_alt = (radix_passes(bits, g.fb) & 1) != 0;
   mark(dev, sl.sort_begin, s);
   radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, g.fb);
   mark(dev, sl.sort, s);
   if (sorted_ev) HLC_TRY(hipEventRecord(sorted_ev, s));
   if (l64 && sd.r64) {
     if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
-    else launch_layout64(sd.vals, sd.cnt, ra, dec, sd.r64, s);
+    else launch_layout64(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r64, s);
   }
   if (l32 && sd.r32) {
     if (sd.src32) launch_gather32(sd.vals, sd.cnt, sd.src32, sd.r32, sd.radec, s);
-    else launch_layout32(sd.vals, sd.cnt, ra, dec, sd.r32, sd.radec, s);
+    else launch_layout32(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r32, sd.radec, s);
   }
   mark(dev, sl.layout, s);
   return HLC_OK;
+}
+
+int partition(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
+              bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd,
+              const Slots& sl, hipStream_t s, hipEvent_t sorted_ev = nullptr) {
+  partition_keys(dev, ra, dec, n, g, halo, l64, l32, sc, err_bit, sd, sl, s);
+  return partition_sort(dev, g, l64, l32, sc, sd, sl, s, sorted_ev);
 }
 
 constexpr Slots NO_SLOTS{-1, -1, -1, -1};
@@ -608,16 +655,16 @@ void fill_stats(const Counters& h, int64_t na, int64_t nb, int64_t nbh, const Ge
   g_stats.zone_height_arcsec = g.h_deg * 3600.0;
 }
 
-// Stage times from the event slots: 0 start; 14 frame known; B partition
-// 1-4 (keygen, sort begin, sort, layout) on the call's stream; A partition
-// 5-7 (keygen, sort, layout) on the side stream from 14 on; 12 both sorts
-// done, 8 ranges done (side stream, beside B's layout); 13 filter start;
-// 9 filter; 10 certification and packing; 11 end. Stages on the two streams
-// overlap, so their times add up to more than the wall time.
+// Stage times from the event slots: 0 start; 14 frame known; 5 A's keygen
+// done and 1 B's keygen done (call's stream, in that order); B's sort and
+// layout 2-4 on the call's stream; A's sort 6 (and 7) on the side stream;
+// 12 both sorts done, 8 ranges done (side stream, beside B's layout); 13
+// filter start; 9 filter; 10 certification and packing; 11 end. Stages on
+// the two streams overlap, so their times add up to more than the wall time.
 void fill_times(Device& dev, bool with_partition) {
   auto el = [&](int a, int b) { return (double)elapsed(dev.ev[a], dev.ev[b]); };
   if (with_partition) {
-    g_stats.t_keygen_ms = el(14, 1) + el(14, 5);
+    g_stats.t_keygen_ms = el(14, 5) + el(5, 1);
     g_stats.t_sort_ms = el(2, 3) + el(5, 6);
     g_stats.t_layout_ms = el(3, 4) + el(6, 7);
     g_stats.t_ranges_ms = el(12, 8);
@@ -648,13 +695,15 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   const bool fp32 = o->precision == HLC_FP32_RECHECK;
   const bool self = (o->flags & HLC_SELF) != 0;
   if (prof) HLC_TRY(hipEventRecord(dev->ev[0], s));
-  Frame f;
-  HLC_CHECK(data_frame(*dev, a_ra, a_dec, self ? 0 : na, b_ra, b_dec, nb, s, &f));
-  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
+  const int64_t na_frame = self ? 0 : na;
+  const unsigned long long seq = frame_sample(*dev, a_ra, a_dec, na_frame, b_ra, b_dec, nb, s);
   const uint32_t nB = (uint32_t)nb;
   // self-match: A's entries are B's (halo copies included)
   const uint32_t nA = self ? 2 * nB : (uint32_t)na;
+  const Slots slB = prof ? Slots{1, 2, 3, 4} : NO_SLOTS;
+  const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
 
+  Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), Frame{});
   Side A, B;
   SortScratch sc, scA;
   MatchWs w;
@@ -668,28 +717,56 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     carve_sort(c, sc, 2 * nB);
     carve_match_ws(c, w, nA, g, caps, true);
   };
+  // While the host waits for the sample, A's keys under the whole-sphere
+  // frame are computed if the previous call on this device had that frame
+  // and the workspace already fits it (the places of A's buffers do not
+  // depend on the frame). They are kept if the sample confirms the frame,
+  // else computed again.
+  bool spec = false;
+  if (!self && dev->last_full) {
+    Carve sizing{nullptr};
+    lay(sizing);
+    if (sizing.off + 256 <= dev->ws_bytes) {
+      Carve c{(char*)dev->ws};
+      lay(c);
+      if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
+      launch_zero_counters(dev->cnt, s);
+      partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, s);
+      spec = true;
+    }
+  }
+  Frame f;
+  HLC_CHECK(frame_finish(*dev, seq, a_ra, a_dec, na_frame, b_ra, b_dec, nb, s, &f));
+  dev->last_full = is_full(f);
+  const bool keep_a = spec && dev->last_full;
+  g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
   Carve sizing{nullptr};
   lay(sizing);
   HLC_CHECK(ensure_ws(*dev, sizing.off + 256));
   Carve c{(char*)dev->ws};
   lay(c);
 
-  if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
-  launch_zero_counters(dev->cnt, s);
+  if (!keep_a) {
+    if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
+    launch_zero_counters(dev->cnt, s);
+  }
   // A's partition on the side stream, B's on the caller's; the ranges run on
   // the side stream once both are sorted, beside B's gather (separate sort
   // scratch, disjoint counter fields)
-  const Slots slB = prof ? Slots{1, 2, 3, 4} : NO_SLOTS;
-  const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
   if (!self) {
+    // A's keys on the caller's stream ahead of B's, so that the hand-over to
+    // the side stream waits under B's keygen
+    if (!keep_a) partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, s);
     HLC_TRY(hipEventRecord(dev->fork, s));
     HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
-    HLC_CHECK(partition(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side));
+    HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
+  } else {
+    mark(*dev, slA.keygen, s);
   }
   HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s, dev->bsorted));
   if (self) {
     // one partition serves both roles; its halo copies are skipped as A
-    for (int k : {slA.keygen, slA.sort, slA.layout}) mark(*dev, k, s);
+    for (int k : {slA.sort, slA.layout}) mark(*dev, k, s);
     A = B;
   }
   HLC_TRY(hipStreamWaitEvent(dev->side, dev->bsorted, 0));
@@ -1986,6 +2063,7 @@ void hlc_shutdown(void) {
     if (d.ws) (void)hipFree(d.ws);
     if (d.cnt) (void)hipFree(d.cnt);
     if (d.cnt_host) (void)hipHostFree(d.cnt_host);
+    if (d.fmsg_host) (void)hipHostFree(d.fmsg_host);
     for (auto& e : d.ev)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : {d.fork, d.bsorted, d.prepped})

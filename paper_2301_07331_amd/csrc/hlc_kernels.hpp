@@ -45,9 +45,11 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits,
                 hipStream_t s, bool from_alt = false, int lo_bit = 0);
 
 // footprint of the valid sources into Counters::ext (max-combined): a
-// sample of at most 2 x 4096 sources (overwrites), or every source (combines)
+// sample of at most 2 x 4096 sources (overwrites; also written to msg[0..3]
+// in mapped host memory, then msg[4] = seq), or every source (combines)
 void launch_extent_sample(const double* ra1, const double* dec1, uint32_t n1, const double* ra2, const double* dec2,
-                          uint32_t n2, Counters* cnt, hipStream_t s);
+                          uint32_t n2, Counters* cnt, unsigned long long* msg, unsigned long long seq,
+                          hipStream_t s);
 void launch_extent(const double* ra, const double* dec, uint32_t n, Counters* cnt, hipStream_t s);
 void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s);
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,

@@ -832,7 +832,11 @@ __device__ inline unsigned long long ord_code(double v) {  // v >= 0
   return (unsigned long long)__double_as_longlong(v);
 }
 
-__device__ inline void ext_reduce(unsigned long long e[4], Counters* cnt, bool block_level) {
+// Block-wide max of e[4] into cnt->ext: atomically (several blocks), or
+// stored (one block; then also mirrored to msg[0..3] in host memory,
+// followed by msg[4] = seq once the four values are visible there).
+__device__ inline void ext_reduce(unsigned long long e[4], Counters* cnt, bool block_level,
+                                  unsigned long long* msg = nullptr, unsigned long long seq = 0ull) {
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     for (int d = 32; d > 0; d >>= 1) {
@@ -844,11 +848,22 @@ __device__ inline void ext_reduce(unsigned long long e[4], Counters* cnt, bool b
   if ((threadIdx.x & 63u) == 0)
     for (int k = 0; k < 4; ++k) s_e[w][k] = e[k];
   __syncthreads();
-  if (threadIdx.x < 4) {
-    unsigned long long m = 0ull;
-    for (uint32_t u = 0; u < (blockDim.x >> 6); ++u) m = s_e[u][threadIdx.x] > m ? s_e[u][threadIdx.x] : m;
-    if (block_level) atomicMax(&cnt->ext[threadIdx.x], m);
-    else cnt->ext[threadIdx.x] = m;
+  if (threadIdx.x == 0) {
+    unsigned long long m[4];
+    for (int k = 0; k < 4; ++k) {
+      m[k] = 0ull;
+      for (uint32_t u = 0; u < (blockDim.x >> 6); ++u) m[k] = s_e[u][k] > m[k] ? s_e[u][k] : m[k];
+    }
+    if (block_level) {
+      for (int k = 0; k < 4; ++k) atomicMax(&cnt->ext[k], m[k]);
+    } else {
+      for (int k = 0; k < 4; ++k) cnt->ext[k] = m[k];
+      if (msg) {
+        for (int k = 0; k < 4; ++k) msg[k] = m[k];
+        __threadfence_system();
+        msg[4] = seq;
+      }
+    }
   }
 }
 
@@ -873,7 +888,8 @@ __device__ inline uint32_t sample_index(uint32_t run, uint32_t lane, uint32_t n)
 __global__ __launch_bounds__(1024) void k_extent_sample(const double* __restrict__ ra1,
                                                         const double* __restrict__ dec1, uint32_t n1,
                                                         const double* __restrict__ ra2,
-                                                        const double* __restrict__ dec2, uint32_t n2, Counters* cnt) {
+                                                        const double* __restrict__ dec2, uint32_t n2, Counters* cnt,
+                                                        unsigned long long* msg, unsigned long long seq) {
   constexpr int PER = 4;  // runs per wave and catalogue (16 waves x 4 = 64 runs)
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   double a[2 * PER], d[2 * PER];
@@ -889,7 +905,7 @@ __global__ __launch_bounds__(1024) void k_extent_sample(const double* __restrict
   unsigned long long e[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
   for (int j = 0; j < 2 * PER; ++j) ext_add(e, a[j], d[j]);
-  ext_reduce(e, cnt, false);
+  ext_reduce(e, cnt, false, msg, seq);
 }
 
 // Every source; one atomic per value and block.
@@ -1002,8 +1018,9 @@ void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, u
 }
 
 void launch_extent_sample(const double* ra1, const double* dec1, uint32_t n1, const double* ra2, const double* dec2,
-                          uint32_t n2, Counters* cnt, hipStream_t s) {
-  k_extent_sample<<<1, 1024, 0, s>>>(ra1, dec1, n1, ra2, dec2, n2, cnt);
+                          uint32_t n2, Counters* cnt, unsigned long long* msg, unsigned long long seq,
+                          hipStream_t s) {
+  k_extent_sample<<<1, 1024, 0, s>>>(ra1, dec1, n1, ra2, dec2, n2, cnt, msg, seq);
 }
 
 void launch_extent(const double* ra, const double* dec, uint32_t n, Counters* cnt, hipStream_t s) {

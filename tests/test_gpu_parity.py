@@ -470,3 +470,21 @@ def test_framed_geometry(hlc, prec):
                "h", round(st["zone_height_arcsec"], 3))
         keys, sep = gpu_xmatch(b_ra, b_dec, a_ra, a_dec, r, prec)
         assert_same(keys, sep, oracle.xmatch(b_ra, b_dec, a_ra, a_dec, r), label=name + " swapped")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_frame_transitions(hlc, prec):
+    """Whole-sphere and framed calls in alternation: A's keys computed ahead under the
+    whole-sphere frame must be kept only when the call's frame is the whole sphere."""
+    g = synth.rng(603, 0)
+    ARC = 1.0 / 3600.0
+    sphere = synth.uniform_sphere(g, 30000)
+    sphere_b = synth.gaussian_offset(g, sphere[0][:12000], sphere[1][:12000], 0.8 * ARC)
+    patch = synth.uniform_patch(g, 30000, 40.0, 40.3, -20.0, -19.7)
+    patch_b = synth.gaussian_offset(g, patch[0][:12000], patch[1][:12000], 0.8 * ARC)
+    cases = {"sphere": (sphere, sphere_b), "patch": (patch, patch_b)}
+    refs = {k: oracle.xmatch(a[0], a[1], b[0], b[1], 2.0) for k, (a, b) in cases.items()}
+    for k in ("sphere", "patch", "patch", "sphere", "sphere", "patch", "sphere"):
+        (a, b) = cases[k]
+        keys, sep = gpu_xmatch(a[0], a[1], b[0], b[1], 2.0, prec)
+        assert_same(keys, sep, refs[k], label=k)

@@ -23,8 +23,8 @@ namespace hlc {
 namespace {
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 4096 keys per tile
+constexpr int RS_ITEMS = 32;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 8192 keys per tile
 constexpr int RS_BINS = 256;
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

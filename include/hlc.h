@@ -187,17 +187,23 @@ int hlc_xmatch_batch(const hlc_job *jobs, int32_t njobs, const double *a_ra, con
                      const double *b_ra, const double *b_dec, hlc_pair *out_pairs,
                      double *out_sep_arcsec, int64_t *job_pair_count, const hlc_opts *opts);
 
-/* Catalogues in pinned HOST memory, streamed to the device in Dec chunks
- * (section 4.3.1: several streams overlap copies and compute; section 4.3.2:
- * page-locked host memory). Pairs are delivered through `sink` in batches
- * from a bounded device ring; `sink` returns 0 to continue, non-zero to
- * abort (the call then returns HLC_E_INVAL). opts->capacity is the ring size
- * in pairs (0 = default); opts->n_pairs receives the total.                 */
+/* Catalogues in pinned HOST memory (section 4.3.2: page-locked host memory).
+ * B is copied to the device once, partitioned once (zones and bins framed by
+ * its footprint widened by r) and kept resident; A follows in slabs of
+ * consecutive sources, two device buffers deep, each slab's copy on its own
+ * stream overlapping the cross-match of the previous slab (section 4.3.1).
+ * Pairs are delivered through `sink` in batches from a bounded device ring
+ * (indices into the caller's full arrays); `sink` returns 0 to continue,
+ * non-zero to abort (the call then returns HLC_E_INVAL). An invalid
+ * coordinate also ends the call with HLC_E_INVAL, after the pairs of the
+ * slabs before it may already have been delivered. opts->capacity is the
+ * ring size in pairs (0 = default); opts->n_pairs receives the total. B must
+ * fit in device memory with its working buffers (about 150 B per source).  */
 typedef int (*hlc_sink)(const hlc_pair *pairs, const double *sep_arcsec, int64_t n, void *user);
-/* The Dec-chunk size is chosen from the eq. (5) transfer model (measured
- * once per device): with per-chunk fixed cost s = alpha_h2d + alpha_d2h +
- * launch overhead and whole-job time W, about sqrt(W / s) chunks balance the
- * fixed costs against the pipeline's fill and drain.                      */
+/* The slab size is chosen from the eq. (5) transfer model (measured once per
+ * device): with per-slab fixed cost s = alpha_h2d + alpha_d2h + launch
+ * overhead and whole-job time W, about sqrt(W / s) slabs balance the fixed
+ * costs against the pipeline's fill and drain.                            */
 int hlc_xmatch_stream(const double *a_ra_host, const double *a_dec_host, int64_t na,
                       const double *b_ra_host, const double *b_dec_host, int64_t nb,
                       double r_arcsec, hlc_sink sink, void *user, const hlc_opts *opts);
@@ -205,7 +211,7 @@ int hlc_xmatch_stream(const double *a_ra_host, const double *a_dec_host, int64_t
 /* Host<->device transfer model of eq. (5): T(d) = alpha + beta * d seconds
  * for d bytes, fitted by least squares to timed pinned-memory copies of 1 B
  * to 64 MiB on the current device (the alpha/beta measurement procedure of
- * section 4.1). The streaming form uses it to size its Dec chunks.        */
+ * section 4.1). The streaming form uses it to size its A slabs.          */
 typedef struct hlc_transfer {
   double alpha_h2d, beta_h2d;  /* s, s/byte */
   double alpha_d2h, beta_d2h;

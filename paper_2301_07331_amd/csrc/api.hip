@@ -241,6 +241,22 @@ double ext_value(unsigned long long code) {
 // box covers over a quarter of the sphere the whole sphere is the frame,
 // otherwise one pass over every source gives the exact box. (The partition
 // keys then resolve a dense patch as finely as the whole sky.)
+// Bounding box of the valid sources from the footprint codes (any: at least
+// one valid source).
+struct Box {
+  bool any;
+  double dlo, dhi, rlo, rhi;
+};
+Box read_box(const Counters& h) {
+  Box b;
+  b.any = h.ext[1] != 0ull;
+  b.dlo = ext_value(~h.ext[0]) - 90.0;
+  b.dhi = ext_value(h.ext[1]) - 90.0;
+  b.rlo = ext_value(~h.ext[2]);
+  b.rhi = ext_value(h.ext[3]);
+  return b;
+}
+
 // Launches the footprint sample of a call; returns its sequence number for
 // frame_finish.
 unsigned long long frame_sample(Device& dev, const double* a_ra, const double* a_dec, int64_t na,
@@ -261,19 +277,7 @@ int frame_finish(Device& dev, unsigned long long seq, const double* a_ra, const 
     HLC_TRY(hipStreamSynchronize(s));
     return HLC_OK;
   };
-  struct Box {
-    bool any;
-    double dlo, dhi, rlo, rhi;
-  };
-  auto box = [&]() {
-    Box b;
-    b.any = hc->ext[1] != 0ull;
-    b.dlo = ext_value(~hc->ext[0]) - 90.0;
-    b.dhi = ext_value(hc->ext[1]) - 90.0;
-    b.rlo = ext_value(~hc->ext[2]);
-    b.rhi = ext_value(hc->ext[3]);
-    return b;
-  };
+  auto box = [&]() { return read_box(*hc); };
   auto quarter_sky = [](const Box& b) {
     const double d2r = M_PI / 180.0;
     return (std::sin(b.dhi * d2r) - std::sin(b.dlo * d2r)) * (b.rhi - b.rlo) * d2r > M_PI;
@@ -1650,10 +1654,12 @@ struct StreamCall {
   Device* d = nullptr;
   hipStream_t s_copy = nullptr, s_d2h = nullptr;
   hipEvent_t ev_copy = nullptr, ev_done = nullptr, ev_d2h[2] = {nullptr, nullptr};
+  hipEvent_t ev_slab[2] = {nullptr, nullptr};  // A slab copied into buffer k
+  hipEvent_t ev_free[2] = {nullptr, nullptr};  // buffer k's slab cross-matched
   ~StreamCall() {
     if (s_copy) (void)hipStreamSynchronize(s_copy);
     if (s_d2h) (void)hipStreamSynchronize(s_d2h);
-    for (hipEvent_t e : {ev_copy, ev_done, ev_d2h[0], ev_d2h[1]})
+    for (hipEvent_t e : {ev_copy, ev_done, ev_d2h[0], ev_d2h[1], ev_slab[0], ev_slab[1], ev_free[0], ev_free[1]})
       if (e) (void)hipEventDestroy(e);
     if (s_copy) (void)hipStreamDestroy(s_copy);
     if (s_d2h) (void)hipStreamDestroy(s_d2h);
@@ -1765,45 +1771,138 @@ int measure_transfer(int dev_id, hlc_transfer* out) {
   return st;
 }
 
-constexpr int32_t STREAM_DEC_BINS = 8192;
-constexpr int64_t STREAM_SLAB = int64_t(1) << 25;  // sources per host->device copy
+// Frame of a streamed call from B's footprint widened by the radius: every
+// A source with a partner lies inside it (A sources outside are clamped into
+// the edge zones and bins, where they find nothing). The whole RA circle when
+// the widened box spans 170 deg or more, crosses RA 0/360 or comes within a
+// degree of a pole.
+Frame frame_around(const Box& b, double r_arcsec) {
+  Frame f;
+  if (!b.any) return f;
+  const double rr = r_arcsec / 3600.0 * (1.0 + 1e-9) + 1e-9;
+  f.dec_lo = std::max(-90.0, b.dlo - rr);
+  f.dec_hi = std::min(90.0, b.dhi + rr);
+  const double dmax = std::max(std::fabs(f.dec_lo), std::fabs(f.dec_hi));
+  if (dmax + rr >= 89.0) return f;
+  const double d2r = M_PI / 180.0;
+  const double D = std::asin(std::min(1.0, std::sin(rr * d2r) / std::cos(dmax * d2r))) / d2r * (1.0 + 1e-9) + 1e-9;
+  const double lo = b.rlo - D, hi = b.rhi + D;
+  if (lo < 0.0 || hi > 360.0 || hi - lo >= 170.0) return f;
+  f.full_ra = false;
+  f.ra_lo = lo;
+  f.ra_span = hi - lo;
+  return f;
+}
 
+// Cross-match of one A slab (device coordinates, m sources) with the
+// partitioned B; pairs into (rp, rs) of capacity cap, their count (or the
+// required count) in *found.
+int slab_match(Device& dev, const double* a_ra, const double* a_dec, uint32_t m, const Side& B,
+               uint32_t* zstartB, const Geom& g, double r_arcsec, bool fp32, Caps& caps, hlc_pair* rp,
+               double* rs, int64_t cap, int64_t* found, const hlc_opts* o, hipStream_t s) {
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    Side A;
+    SortScratch scA;
+    MatchWs w;
+    auto lay = [&](Carve& c) {
+      carve_side(c, A, m, !fp32, fp32, m, false);
+      carve_sort(c, scA, m);
+      carve_match_ws(c, w, m, g, caps, false);
+    };
+    Carve sizing{nullptr};
+    lay(sizing);
+    HLC_CHECK(ensure_ws(dev, sizing.off + 256));
+    Carve c{(char*)dev.ws};
+    lay(c);
+    w.zstartB = zstartB;
+    launch_zero_counters(dev.cnt, s);
+    partition_keys(dev, a_ra, a_dec, m, g, false, !fp32, fp32, scA, 1u, A, NO_SLOTS, s);
+    HLC_CHECK(partition_sort(dev, g, !fp32, fp32, scA, A, NO_SLOTS, s));
+    match(dev, A, B, g, r_arcsec, fp32, false, false, Radii{nullptr, nullptr, 0.0}, w, rp,
+          (o->flags & HLC_NO_SEP) ? nullptr : rs, (uint64_t)cap, false, tuned_items(o), s);
+    HLC_CHECK(read_counters(dev, s, false));
+    const Counters& h = *dev.cnt_host;
+    if (h.err) return HLC_E_INVAL;
+    if (regrow(dev, h, (uint64_t)cap, caps)) continue;
+    *found = (int64_t)h.n_pairs;
+    return h.n_pairs > (unsigned long long)cap ? HLC_E_OVERFLOW : HLC_OK;
+  }
+  return HLC_E_NOMEM;
+}
+
+// Streaming form. B is copied once, partitioned once (frame from its
+// footprint) and stays resident; A follows in input-order slabs, two device
+// buffers deep, each slab's copy overlapping the previous slab's
+// cross-match. Each slab's pairs go back through one half of a device ring
+// while the other half is being filled. Slabs are sized from the eq. (5)
+// transfer model.
 int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const double* b_ra_h,
                 const double* b_dec_h, int64_t nb, double r_arcsec, hlc_sink sink, void* user,
                 const hlc_opts* o) {
   Device* dev = nullptr;
   HLC_CHECK(get_device(&dev));
   hipStream_t s = (hipStream_t)o->stream;
+  const bool fp32 = o->precision == HLC_FP32_RECHECK;
+  std::memset(&g_stats, 0, sizeof(g_stats));
+  g_stats.na = na;
+  g_stats.nb = nb;
+  *o->n_pairs = 0;
   StreamCall sc;
   sc.d = dev;
-  HLC_TRY(hipStreamCreate(&sc.s_copy));
-  HLC_TRY(hipStreamCreate(&sc.s_d2h));
+  // non-blocking: a caller on the legacy null stream would otherwise
+  // serialise the copies with the compute (every dependency is an event)
+  HLC_TRY(hipStreamCreateWithFlags(&sc.s_copy, hipStreamNonBlocking));
+  HLC_TRY(hipStreamCreateWithFlags(&sc.s_d2h, hipStreamNonBlocking));
   HLC_TRY(hipEventCreateWithFlags(&sc.ev_copy, hipEventDisableTiming));
   HLC_TRY(hipEventCreateWithFlags(&sc.ev_done, hipEventDisableTiming));
-  for (auto& e : sc.ev_d2h) HLC_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto* e : {&sc.ev_d2h[0], &sc.ev_d2h[1], &sc.ev_slab[0], &sc.ev_slab[1], &sc.ev_free[0], &sc.ev_free[1]})
+    HLC_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  for (hipEvent_t e : sc.ev_free) HLC_TRY(hipEventRecord(e, s));  // both A buffers start free
+
+  // A slab size: with per-slab fixed cost s_fix = alpha_h2d + alpha_d2h +
+  // launch overhead (about 30 launches and two synchronisations) and
+  // whole-job time W (A over the link, about one pair per A source back,
+  // compute at ~3e9 sources/s), about sqrt(W / s_fix) slabs balance the
+  // fixed costs against the pipeline's fill and drain.
+  int dev_id = 0;
+  HLC_TRY(hipGetDevice(&dev_id));
+  hlc_transfer tm{};
+  int64_t SLAB = int64_t(1) << 24;
+  if (measure_transfer(dev_id, &tm) == HLC_OK && tm.beta_h2d > 0 && tm.beta_d2h > 0) {
+    const double s_fix = std::max(tm.alpha_h2d, 0.0) + std::max(tm.alpha_d2h, 0.0) + 3.0e-4;
+    const double W = tm.beta_h2d * 16.0 * (double)na + tm.beta_d2h * 16.0 * (double)na + (double)na / 3.0e9;
+    const double k = std::sqrt(W / s_fix);
+    SLAB = (int64_t)std::min(std::max((double)na / std::max(k, 1.0), 1048576.0), 33554432.0);
+  }
+  SLAB = std::max<int64_t>(std::min<int64_t>(SLAB, na), 1);
+  const int64_t nslab = (na + SLAB - 1) / SLAB;
 
   // ring: two halves, each drained to its own pinned host staging area
   const int64_t ring = o->capacity > 0 ? o->capacity : (int64_t(1) << 25);
   const int64_t half = std::max<int64_t>(ring / 2, 1024);
+  const uint32_t nB = (uint32_t)nb;
   hlc_pair* d_pairs;
   double* d_sep;
-  double *A_ra, *A_dec, *B_ra, *B_dec;
-  uint32_t* hist;
-  int32_t* d_cob;
-  double* d_edges;
-  unsigned long long *curA, *curB;
+  double *B_ra, *B_dec;
+  uint32_t* zstartB;
+  Side B;
+  SortScratch scB;
   auto lay0 = [&](Carve& c) {
     d_pairs = c.take<hlc_pair>(2 * half);
     d_sep = c.take<double>(2 * half);
-    A_ra = c.take<double>(std::max<int64_t>(na, 1));
-    A_dec = c.take<double>(std::max<int64_t>(na, 1));
-    B_ra = c.take<double>(std::max<int64_t>(nb, 1));
-    B_dec = c.take<double>(std::max<int64_t>(nb, 1));
-    hist = c.take<uint32_t>(2 * STREAM_DEC_BINS);
-    d_cob = c.take<int32_t>(STREAM_DEC_BINS);
-    d_edges = c.take<double>(STREAM_DEC_BINS + 2);
-    curA = c.take<unsigned long long>(STREAM_DEC_BINS + 1);
-    curB = c.take<unsigned long long>(STREAM_DEC_BINS + 1);
+    B_ra = c.take<double>(std::max(nB, 1u));
+    B_dec = c.take<double>(std::max(nB, 1u));
+    carve_side(c, B, 2 * nB, !fp32, fp32, nB);
+    carve_sort(c, scB, 2 * nB);
+    zstartB = c.take<uint32_t>(65537);
+  };
+  double* A_ra[2];
+  double* A_dec[2];
+  auto lay1 = [&](Carve& c) {
+    for (int k = 0; k < 2; ++k) {
+      A_ra[k] = c.take<double>((size_t)SLAB);
+      A_dec[k] = c.take<double>((size_t)SLAB);
+    }
   };
   {
     Carve z{nullptr};
@@ -1811,6 +1910,11 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
     HLC_CHECK(sc.reserve(0, z.off + 256));
     Carve c{(char*)dev->sarena[0]};
     lay0(c);
+    Carve z1{nullptr};
+    lay1(z1);
+    HLC_CHECK(sc.reserve(1, z1.off + 256));
+    Carve c1{(char*)dev->sarena[1]};
+    lay1(c1);
   }
   hlc_pair* h_pairs[2];
   double* h_sep[2];
@@ -1824,115 +1928,48 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
       hp += (size_t)half * sizeof(double);
     }
   }
-
-  // 1. copy both catalogues in slabs; a Dec histogram of each slab runs on
-  //    the compute stream while the next slab is in flight
-  HLC_TRY(hipMemsetAsync(hist, 0, 2 * STREAM_DEC_BINS * sizeof(uint32_t), s));
-  launch_zero_counters(dev->cnt, s);
-  HLC_TRY(hipStreamSynchronize(s));
-  struct Src {
-    const double *ra_h, *dec_h;
-    double *ra, *dec;
-    int64_t n;
-    uint32_t* hist;
-    uint32_t err;
-  } srcs[2] = {{a_ra_h, a_dec_h, A_ra, A_dec, na, hist, 1u},
-               {b_ra_h, b_dec_h, B_ra, B_dec, nb, hist + STREAM_DEC_BINS, 2u}};
-  for (const Src& x : srcs) {
-    for (int64_t off = 0; off < x.n; off += STREAM_SLAB) {
-      const int64_t m = std::min(STREAM_SLAB, x.n - off);
-      HLC_TRY(hipMemcpyAsync(x.ra + off, x.ra_h + off, m * 8, hipMemcpyHostToDevice, sc.s_copy));
-      HLC_TRY(hipMemcpyAsync(x.dec + off, x.dec_h + off, m * 8, hipMemcpyHostToDevice, sc.s_copy));
-      HLC_TRY(hipEventRecord(sc.ev_copy, sc.s_copy));
-      HLC_TRY(hipStreamWaitEvent(s, sc.ev_copy, 0));
-      launch_dec_hist(x.ra + off, x.dec + off, (uint32_t)m, STREAM_DEC_BINS, x.hist, x.err, dev->cnt, s);
-    }
-  }
-  std::vector<uint32_t> h_hist(2 * STREAM_DEC_BINS);
-  HLC_TRY(hipMemcpyAsync(h_hist.data(), hist, h_hist.size() * 4, hipMemcpyDeviceToHost, s));
-  HLC_TRY(hipMemcpyAsync(dev->cnt_host, dev->cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-  HLC_TRY(hipStreamSynchronize(s));
-  if (dev->cnt_host->err) return HLC_E_INVAL;
-
-  // 2. Dec chunks: consecutive histogram bins holding <= CHUNK A sources
-  //    (a single dense bin may exceed it). With per-chunk fixed cost
-  //    s = alpha_h2d + alpha_d2h + launch overhead (about 25 launches of
-  //    ~5 us and two synchronisations) and whole-job time W (inputs over the
-  //    link, one pair per A source back, compute at ~2e9 sources/s), about
-  //    sqrt(W / s) chunks balance the fixed costs against fill and drain.
-  int dev_id = 0;
-  HLC_TRY(hipGetDevice(&dev_id));
-  hlc_transfer tm{};
-  int64_t CHUNK = int64_t(1) << 23;
-  if (measure_transfer(dev_id, &tm) == HLC_OK && tm.beta_h2d > 0 && tm.beta_d2h > 0) {
-    const double s_fix = std::max(tm.alpha_h2d, 0.0) + std::max(tm.alpha_d2h, 0.0) + 2.0e-4;
-    const double W = tm.beta_h2d * 16.0 * (double)(na + nb) + tm.beta_d2h * 16.0 * (double)na +
-                     (double)(na + nb) / 2.0e9;
-    const double k = std::sqrt(W / s_fix);
-    CHUNK = (int64_t)std::min(std::max((double)na / std::max(k, 1.0), 1.0e6), 3.2e7);
-  }
-  std::vector<int32_t> chunk_of_bin(STREAM_DEC_BINS);
-  std::vector<double> edges{-90.0};
-  int64_t acc = 0;
-  int32_t nch = 0;
-  for (int32_t b = 0; b < STREAM_DEC_BINS; ++b) {
-    int64_t c = h_hist[b];
-    if (acc > 0 && acc + c > CHUNK) {
-      edges.push_back(-90.0 + 180.0 * b / STREAM_DEC_BINS);
-      ++nch;
-      acc = 0;
-    }
-    acc += c;
-    chunk_of_bin[b] = nch;
-  }
-  ++nch;
-  edges.push_back(90.0);
-  HLC_TRY(hipMemcpyAsync(d_cob, chunk_of_bin.data(), STREAM_DEC_BINS * 4, hipMemcpyHostToDevice, s));
-  HLC_TRY(hipMemcpyAsync(d_edges, edges.data(), edges.size() * 8, hipMemcpyHostToDevice, s));
-  // B counts per chunk including the copies for neighbouring chunks
-  Geom gr;
-  set_radius(gr, r_arcsec);
-  HLC_TRY(hipMemsetAsync(curB, 0, nch * 8, s));
-  launch_chunk_scatter(B_ra, B_dec, (uint32_t)nb, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, gr.rpad_deg,
-                       curB, nullptr, nullptr, nullptr, s);
-  std::vector<unsigned long long> cntB(nch), offA(nch + 1, 0), offB(nch + 1, 0);
-  HLC_TRY(hipMemcpyAsync(cntB.data(), curB, nch * 8, hipMemcpyDeviceToHost, s));
-  HLC_TRY(hipStreamSynchronize(s));
-  for (int32_t b = 0; b < STREAM_DEC_BINS; ++b) offA[chunk_of_bin[b] + 1] += h_hist[b];
-  for (int32_t k = 0; k < nch; ++k) {
-    offA[k + 1] += offA[k];
-    offB[k + 1] = offB[k] + cntB[k];
-  }
-  // 3. chunk-ordered copies with original indices
-  double *CA_ra, *CA_dec, *CB_ra, *CB_dec;
-  uint32_t *CA_idx, *CB_idx;
-  auto lay1 = [&](Carve& c) {
-    const size_t nA = std::max<int64_t>(na, 1), nB = std::max<uint64_t>(offB[nch], 1);
-    CA_ra = c.take<double>(nA);
-    CA_dec = c.take<double>(nA);
-    CA_idx = c.take<uint32_t>(nA);
-    CB_ra = c.take<double>(nB);
-    CB_dec = c.take<double>(nB);
-    CB_idx = c.take<uint32_t>(nB);
+  auto copy_slab = [&](int64_t k) -> int {
+    const int b = (int)(k & 1);
+    const int64_t a0 = k * SLAB, m = std::min(SLAB, na - a0);
+    // the buffer's previous slab must be done with it
+    HLC_TRY(hipStreamWaitEvent(sc.s_copy, sc.ev_free[b], 0));
+    HLC_TRY(hipMemcpyAsync(A_ra[b], a_ra_h + a0, (size_t)m * 8, hipMemcpyHostToDevice, sc.s_copy));
+    HLC_TRY(hipMemcpyAsync(A_dec[b], a_dec_h + a0, (size_t)m * 8, hipMemcpyHostToDevice, sc.s_copy));
+    HLC_TRY(hipEventRecord(sc.ev_slab[b], sc.s_copy));
+    return HLC_OK;
   };
-  {
-    Carve z{nullptr};
-    lay1(z);
-    HLC_CHECK(sc.reserve(1, z.off + 256));
-    Carve c{(char*)dev->sarena[1]};
-    lay1(c);
-  }
-  HLC_TRY(hipMemcpyAsync(curA, offA.data(), nch * 8, hipMemcpyHostToDevice, s));
-  HLC_TRY(hipMemcpyAsync(curB, offB.data(), nch * 8, hipMemcpyHostToDevice, s));
-  launch_chunk_scatter(A_ra, A_dec, (uint32_t)na, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, 0.0, curA,
-                       CA_ra, CA_dec, CA_idx, s);
-  launch_chunk_scatter(B_ra, B_dec, (uint32_t)nb, 0, STREAM_DEC_BINS, d_cob, d_edges, nch, gr.rpad_deg,
-                       curB, CB_ra, CB_dec, CB_idx, s);
 
-  // 4. chunks through the core cross-match; pairs leave through the ring
+  // 1. B, then the first A slab, over the link
+  if (nB) {
+    HLC_TRY(hipMemcpyAsync(B_ra, b_ra_h, (size_t)nB * 8, hipMemcpyHostToDevice, sc.s_copy));
+    HLC_TRY(hipMemcpyAsync(B_dec, b_dec_h, (size_t)nB * 8, hipMemcpyHostToDevice, sc.s_copy));
+  }
+  HLC_TRY(hipEventRecord(sc.ev_copy, sc.s_copy));
+  if (nslab > 0) HLC_CHECK(copy_slab(0));
+  HLC_TRY(hipStreamWaitEvent(s, sc.ev_copy, 0));
+
+  // 2. the frame from B's footprint; B partitioned once
+  launch_zero_counters(dev->cnt, s);
+  launch_extent(B_ra, B_dec, nB, dev->cnt, s);
+  HLC_CHECK(read_counters(*dev, s, false));
+  const Frame f = frame_around(read_box(*dev->cnt_host), r_arcsec);
+  const Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
+  launch_zero_counters(dev->cnt, s);
+  HLC_CHECK(partition(*dev, B_ra, B_dec, nB, g, true, !fp32, fp32, scB, 2u, B, NO_SLOTS, s));
+  launch_zone_starts(B.keys, B.cnt, g, zstartB, s);
+  HLC_CHECK(read_counters(*dev, s, false));
+  if (dev->cnt_host->err) return HLC_E_INVAL;
+  const uint32_t ne = nB + (uint32_t)dev->cnt_host->n_halo;
+  B.cnt = DevCount{ne, ne, nullptr};  // final: the counters are reused per slab
+  g_stats.nb_halo = ne;
+  g_stats.n_zones = g.nz;
+  g_stats.ra_bits = g.rb;
+  g_stats.zone_height_arcsec = g.h_deg * 3600.0;
+
+  // 3. A slabs through the cross-match; pairs leave through the ring
   int64_t total = 0;
   int64_t pending[2] = {-1, -1};
-  int32_t slot = 0;
+  int slot = 0;
   auto drain = [&](int h) -> int {
     if (pending[h] < 0) return HLC_OK;
     HLC_TRY(hipEventSynchronize(sc.ev_d2h[h]));
@@ -1942,56 +1979,51 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
       return HLC_E_INVAL;
     return HLC_OK;
   };
-  struct Work {
-    uint64_t a0, na, b0, nb;
-  };
-  std::vector<Work> todo;
-  for (int32_t k = nch - 1; k >= 0; --k)
-    todo.push_back({offA[k], offA[k + 1] - offA[k], offB[k], offB[k + 1] - offB[k]});
-  hlc_opts co = *o;
-  co.capacity = half;
-  co.flags = o->flags & (HLC_NO_SEP | HLC_PROFILE);
-  int64_t nfound = 0;
-  co.n_pairs = &nfound;
-  while (!todo.empty()) {
-    Work w = todo.back();
-    todo.pop_back();
-    if (w.na == 0 || w.nb == 0) continue;
-    HLC_CHECK(drain(slot));  // this half's previous batch has reached the host
-    hlc_pair* rp = d_pairs + slot * half;
-    double* rs = d_sep + slot * half;
-    int st = xmatch_core(CA_ra + w.a0, CA_dec + w.a0, (int64_t)w.na, CB_ra + w.b0, CB_dec + w.b0,
-                         (int64_t)w.nb, r_arcsec, rp, rs, &co);
-    if (st == HLC_E_OVERFLOW) {
-      if (w.na == 1) return HLC_E_OVERFLOW;  // one source has more pairs than half the ring
-      const uint64_t h1 = w.na / 2;
-      todo.push_back({w.a0 + h1, w.na - h1, w.b0, w.nb});
-      todo.push_back({w.a0, h1, w.b0, w.nb});
-      continue;
+  Caps caps = initial_caps(*dev, 2 * (uint64_t)SLAB, (uint64_t)half, true);
+  for (int64_t k = 0; k < nslab; ++k) {
+    const int b = (int)(k & 1);
+    const int64_t a0 = k * SLAB, m = std::min(SLAB, na - a0);
+    if (k + 1 < nslab) HLC_CHECK(copy_slab(k + 1));
+    HLC_TRY(hipStreamWaitEvent(s, sc.ev_slab[b], 0));
+    // sub-ranges of the slab: a range with more pairs than half the ring is
+    // split in two
+    std::vector<std::pair<int64_t, int64_t>> todo{{0, m}};
+    while (!todo.empty()) {
+      const auto [u0, um] = todo.back();
+      todo.pop_back();
+      if (um == 0) continue;
+      HLC_CHECK(drain(slot));  // this half's previous batch has reached the host
+      hlc_pair* rp = d_pairs + slot * half;
+      double* rs = d_sep + slot * half;
+      int64_t found = 0;
+      const int st = slab_match(*dev, A_ra[b] + u0, A_dec[b] + u0, (uint32_t)um, B, zstartB, g, r_arcsec, fp32,
+                                caps, rp, rs, half, &found, o, s);
+      if (st == HLC_E_OVERFLOW) {
+        if (um == 1) return HLC_E_OVERFLOW;  // one source has more pairs than half the ring
+        const int64_t h1 = um / 2;
+        todo.push_back({u0 + h1, um - h1});
+        todo.push_back({u0, h1});
+        continue;
+      }
+      if (st != HLC_OK) return st;
+      launch_offset_pairs(reinterpret_cast<uint2*>(rp), (uint32_t)found, (uint32_t)(a0 + u0), s);
+      HLC_TRY(hipEventRecord(sc.ev_done, s));
+      HLC_TRY(hipStreamWaitEvent(sc.s_d2h, sc.ev_done, 0));
+      if (found > 0) {
+        HLC_TRY(hipMemcpyAsync(h_pairs[slot], rp, found * sizeof(hlc_pair), hipMemcpyDeviceToHost, sc.s_d2h));
+        if (!(o->flags & HLC_NO_SEP))
+          HLC_TRY(hipMemcpyAsync(h_sep[slot], rs, found * sizeof(double), hipMemcpyDeviceToHost, sc.s_d2h));
+      }
+      HLC_TRY(hipEventRecord(sc.ev_d2h[slot], sc.s_d2h));
+      pending[slot] = found;
+      total += found;
+      slot ^= 1;
     }
-    if (st != HLC_OK) return st;
-    const int64_t n = nfound;
-    launch_remap_pairs(reinterpret_cast<uint2*>(rp), (uint32_t)n, CA_idx + w.a0, CB_idx + w.b0, s);
-    HLC_TRY(hipEventRecord(sc.ev_done, s));
-    HLC_TRY(hipStreamWaitEvent(sc.s_d2h, sc.ev_done, 0));
-    if (n > 0) {
-      HLC_TRY(hipMemcpyAsync(h_pairs[slot], rp, n * sizeof(hlc_pair), hipMemcpyDeviceToHost, sc.s_d2h));
-      if (!(o->flags & HLC_NO_SEP))
-        HLC_TRY(hipMemcpyAsync(h_sep[slot], rs, n * sizeof(double), hipMemcpyDeviceToHost, sc.s_d2h));
-    }
-    HLC_TRY(hipEventRecord(sc.ev_d2h[slot], sc.s_d2h));
-    pending[slot] = n;
-    total += n;
-    slot ^= 1;
+    HLC_TRY(hipEventRecord(sc.ev_free[b], s));
   }
   HLC_CHECK(drain(slot));
   HLC_CHECK(drain(slot ^ 1));
-  std::memset(&g_stats, 0, sizeof(g_stats));
-  g_stats.na = na;
-  g_stats.nb = nb;
-  g_stats.nb_halo = (int64_t)offB[nch];
   g_stats.n_pairs = total;
-  g_stats.n_zones = nch;  // Dec chunks
   *o->n_pairs = total;
   return HLC_OK;
 }

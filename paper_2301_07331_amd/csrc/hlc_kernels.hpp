@@ -220,15 +220,8 @@ void launch_equal_ranges(const uint32_t* keysA, const DevCount& na, const uint32
                          const DevCount& nb, GroupRanges* out, hipStream_t s);
 
 // ---- stream.hip ------------------------------------------------------------
-void launch_dec_hist(const double* ra, const double* dec, uint32_t n, int32_t nbins, uint32_t* hist,
-                     uint32_t err_bit, Counters* cnt, hipStream_t s);
-// out_ra == nullptr: count only (cursor[k] += entries of chunk k)
-void launch_chunk_scatter(const double* ra, const double* dec, uint32_t n, uint32_t base_index,
-                          int32_t nbins, const int32_t* chunk_of_bin, const double* edges,
-                          int32_t nchunks, double halo_deg, unsigned long long* cursor,
-                          double* out_ra, double* out_dec, uint32_t* out_idx, hipStream_t s);
-void launch_remap_pairs(uint2* pairs, uint32_t n, const uint32_t* a_idx, const uint32_t* b_idx,
-                        hipStream_t s);
+// pairs[i].a += a_off for i < n
+void launch_offset_pairs(uint2* pairs, uint32_t n, uint32_t a_off, hipStream_t s);
 
 // ---- batch.hip -------------------------------------------------------------
 struct BatchJob {          // one job as given by the caller, plus host-derived fields

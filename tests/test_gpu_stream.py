@@ -1,4 +1,4 @@
-"""GPU: the streaming form (host catalogues, Dec chunks, bounded ring) against the oracle."""
+"""GPU: the streaming form (host catalogues, resident B, A slabs, bounded ring) against the oracle."""
 import numpy as np
 import pytest
 

@@ -448,9 +448,12 @@ struct KeyIndex {
   int shift;
   uint32_t T;
 };
+// (never finer than the sorted key bits: the low fb bits of a sorted key
+// array are in input order within a bin, so the index is exact only on
+// multiples of 2^fb)
 KeyIndex key_index_dims(const Geom& g) {
   const int kb = key_bits(g);
-  const int shift = std::max(6, kb - 18);
+  const int shift = std::max(std::max(6, kb - 18), g.fb);
   return KeyIndex{shift, (uint32_t)((1ull << std::max(kb - shift, 0)) + 1)};
 }
 

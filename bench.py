@@ -24,15 +24,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per launch of the filter kernel (the dominant kernel):
-# the working records of both sides read once, each staged candidate (A's
-# FP64 data, A index, B position: 32 B) written once.
-#   FP64 form: 32 B per A record, 32 B per B entry (x, y, z f64 + index).
-#   FP32 form: 32 B per A record (x, y, z f32 + index + FP64 ra, dec, which
-#              the candidates carry), 16 B per B entry (x, y, z f32 + index).
+# Algorithmic bytes per launch of the match (filter) kernel: the working
+# layout of every A source and every B entry (halo copies included) read
+# once, which is what the method must move:
+#   FP64 form: 28 B per entry (x, y, z f64 + u32 index).
+#   FP32 form: 16 B per entry (x, y, z f32 + u32 index), plus 32 B per
+#              candidate inside the certified band (its FP64 re-read).
+# What the kernel actually moves (its 32-B in-place A records, one cache
+# line each, and its staged candidates) is the measured `traffic`.
 MATCH_BYTES = {
-    "fp64": lambda na, nbh, npairs, ncand: 32 * na + 32 * nbh + 32 * ncand,
-    "fp32": lambda na, nbh, npairs, ncand: 32 * na + 16 * nbh + 32 * ncand,
+    "fp64": lambda na, nbh, nband: 28 * (na + nbh),
+    "fp32": lambda na, nbh, nband: 16 * (na + nbh) + 32 * nband,
 }
 # Whole-call canonical bytes: FP64 (ra, dec) of every source read once and
 # every pair written once.
@@ -301,7 +303,7 @@ def main():
         stage = {k: statistics.median(s[k] for s in stats)
                  for k in ("t_keygen_ms", "t_sort_ms", "t_layout_ms", "t_ranges_ms", "t_match_ms",
                            "t_certify_ms", "t_total_ms")}
-        mb = MATCH_BYTES[name](na, s0["nb_halo"], s0["n_pairs"], s0["n_candidates"])
+        mb = MATCH_BYTES[name](na, s0["nb_halo"], s0["n_band"])
         results[name] = dict(ms_per_step=ms, n_pairs=int(n), stage_ms=stage, nb_halo=int(s0["nb_halo"]),
                              n_candidates=int(s0["n_candidates"]), n_band=int(s0["n_band"]),
                              n_ties=int(s0["n_ties"]), zone_height_arcsec=s0["zone_height_arcsec"],

@@ -59,6 +59,28 @@ def test_stream_errors_and_abort(hlc):
     assert st == hlc.HLC_E_INVAL
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_stream_several_slabs_full_oracle(hlc, prec):
+    """3M A in slabs of about 1M (copies overlapping the cross-match), a patch with A
+    outliers far from B and just outside its footprint; the whole set against the oracle."""
+    g = synth.rng(401, 0)
+    a_ra, a_dec = synth.uniform_patch(g, 3_000_000, 150.0, 152.0, 0.0, 2.0)
+    b_ra, b_dec = synth.uniform_patch(g, 1_000_000, 150.0, 152.0, 0.0, 2.0)
+    # A sources outside B's footprint (clamped into the edge zones and bins)
+    a_ra[:1000] = g.uniform(0.0, 360.0, 1000)
+    a_dec[:1000] = g.uniform(-89.0, 89.0, 1000)
+    # A just outside B's box, within r of its edge
+    a_ra[1000:1100] = 150.0 - g.uniform(0.0, 2e-4, 100)
+    a_dec[1000:1100] = g.uniform(0.0, 2.0, 100)
+    r = 1.0
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+    pairs, sep = hlc.xmatch_stream(_pinned(a_ra), _pinned(a_dec), _pinned(b_ra), _pinned(b_dec), r,
+                                   precision=prec, ring_pairs=1 << 20)
+    k = _keys(pairs)
+    o = np.argsort(k)
+    assert_same(k[o], sep[o], ref, label=f"slabs prec={prec}")
+
+
 def test_stream_large_400M_x_100M_sampled(hlc):
     """The large workload at full size: every pair of a random sample of A sources checked."""
     import time

@@ -75,19 +75,36 @@ __global__ __launch_bounds__(FT) void k_job_bounds(const BatchTile* __restrict__
       atomicOr(&cnt->err, side_b ? 2u : 1u);
     }
   }
-  // wave reductions, one atomic per wave and bound
+  // wave, then block reductions: one atomic per block and bound
   for (int off = 32; off > 0; off >>= 1) {
     dmin = fmin(dmin, __shfl_xor(dmin, off));
     dmax = fmax(dmax, __shfl_xor(dmax, off));
     omin = fmin(omin, __shfl_xor(omin, off));
     omax = fmax(omax, __shfl_xor(omax, off));
   }
-  if ((threadIdx.x & 63) == 0 && dmin <= dmax) {
-    unsigned long long* b = bounds + 4 * (size_t)T.job;
-    atomicMin(&b[0], ord_enc(dmin));
-    atomicMax(&b[1], ord_enc(dmax));
-    atomicMin(&b[2], ord_enc(omin));
-    atomicMax(&b[3], ord_enc(omax));
+  __shared__ double s_b[FT / 64][4];
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_b[w][0] = dmin;
+    s_b[w][1] = dmax;
+    s_b[w][2] = omin;
+    s_b[w][3] = omax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t u = 1; u < (blockDim.x + 63u) / 64u; ++u) {
+      dmin = fmin(dmin, s_b[u][0]);
+      dmax = fmax(dmax, s_b[u][1]);
+      omin = fmin(omin, s_b[u][2]);
+      omax = fmax(omax, s_b[u][3]);
+    }
+    if (dmin <= dmax) {
+      unsigned long long* b = bounds + 4 * (size_t)T.job;
+      atomicMin(&b[0], ord_enc(dmin));
+      atomicMax(&b[1], ord_enc(dmax));
+      atomicMin(&b[2], ord_enc(omin));
+      atomicMax(&b[3], ord_enc(omax));
+    }
   }
 }
 
@@ -244,14 +261,27 @@ __global__ __launch_bounds__(256) void k_batch_keygen(const BatchTile* __restric
   const int32_t zl = job_zone(G, d - G.rpad_deg), zh = job_zone(G, d + G.rpad_deg);
   const int32_t other = (zl != z) ? zl : zh;
   const bool need = ok && other != z;
+  // the block's halo copies placed with one atomic on the shared counter
+  // (one per wave serialised every wave of the batch on one address)
+  __shared__ uint32_t s_wc[4];
+  __shared__ unsigned long long s_base[4];
   const uint64_t m = __ballot(need);
-  if (m == 0) return;
-  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(&cnt->n_halo, (unsigned long long)__popcll(m));
-  base = __shfl(base, (int)leader);
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) s_wc[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nw = (blockDim.x + 63u) >> 6;
+    unsigned long long tot = 0;
+    for (uint32_t u = 0; u < nw; ++u) tot += s_wc[u];
+    unsigned long long base = tot ? atomicAdd(&cnt->n_halo, tot) : 0ull;
+    for (uint32_t u = 0; u < nw; ++u) {
+      s_base[u] = base;
+      base += s_wc[u];
+    }
+  }
+  __syncthreads();
   if (need) {
-    const uint64_t pos = (uint64_t)n_total + base + rank_in(m);
+    const uint64_t pos = (uint64_t)n_total + s_base[w] + rank_in(m);
     keys[pos] = jb | ((uint32_t)other << G.rb) | b;
     vals[pos] = src | HALO_BIT;
   }

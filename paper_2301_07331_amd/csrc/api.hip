@@ -1274,12 +1274,12 @@ int build_plan(const hlc_job* jobs, int32_t njobs, BatchPlan& P) {
     B.zcap = (uint32_t)std::min<uint64_t>(zmax, 4 + (uint64_t)(J.na + J.nb) / 16);
     B.zoff = (uint32_t)zo;
     zo += B.zcap + 1;
-    for (int64_t t = 0; t < J.na; t += 256)
+    for (int64_t t = 0; t < J.na; t += BATCH_TILE)
       P.tA.push_back({(uint32_t)j, (uint32_t)(ea + t), (uint32_t)(J.a_off + t),
-                      (uint32_t)std::min<int64_t>(256, J.na - t)});
-    for (int64_t t = 0; t < J.nb; t += 256)
+                      (uint32_t)std::min<int64_t>(BATCH_TILE, J.na - t)});
+    for (int64_t t = 0; t < J.nb; t += BATCH_TILE)
       P.tB.push_back({(uint32_t)j, (uint32_t)(eb + t), (uint32_t)(J.b_off + t),
-                      (uint32_t)std::min<int64_t>(256, J.nb - t)});
+                      (uint32_t)std::min<int64_t>(BATCH_TILE, J.nb - t)});
     ea += J.na;
     eb += J.nb;
     if (ea >= (uint64_t(1) << 30) || eb >= (uint64_t(1) << 30) || zo >= (uint64_t(1) << 31))

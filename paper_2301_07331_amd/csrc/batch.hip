@@ -23,7 +23,8 @@ namespace {
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-constexpr int FT = 256;  // threads of the bounds kernel
+constexpr int FT = 256;              // threads of the per-tile kernels
+constexpr int TI = BATCH_TILE / FT;  // sources per thread
 
 __device__ inline double fold180(double x) {
   // x in (-360, 360] -> (-180, 180]
@@ -64,17 +65,35 @@ __global__ __launch_bounds__(FT) void k_job_bounds(const BatchTile* __restrict__
                                                    unsigned long long* __restrict__ bounds, Counters* cnt) {
   if (blockIdx.x >= ntiles) return;
   const BatchTile T = tiles[blockIdx.x];
-  const double ref = job_ref_ra(jobs[T.job], a_ra, b_ra);
-  double dmin = 1e300, dmax = -1e300, omin = 1e300, omax = -1e300;
-  if (threadIdx.x < T.count) {
-    const double a = ra[T.src + threadIdx.x], d = dec[T.src + threadIdx.x];
-    if (valid_pos(a, d)) {
-      dmin = dmax = d;
-      omin = omax = fold180(a - ref);
-    } else {
-      atomicOr(&cnt->err, side_b ? 2u : 1u);
+  // the tile's positions are in flight while the job's reference RA is read
+  double av[TI], dv[TI];
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    const uint32_t k = j * FT + threadIdx.x;
+    av[j] = 0.0;
+    dv[j] = 0.0;
+    if (k < T.count) {
+      av[j] = ra[T.src + k];
+      dv[j] = dec[T.src + k];
     }
   }
+  const double ref = job_ref_ra(jobs[T.job], a_ra, b_ra);
+  double dmin = 1e300, dmax = -1e300, omin = 1e300, omax = -1e300;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    if (j * FT + threadIdx.x >= T.count) continue;
+    if (valid_pos(av[j], dv[j])) {
+      dmin = fmin(dmin, dv[j]);
+      dmax = fmax(dmax, dv[j]);
+      const double o = fold180(av[j] - ref);
+      omin = fmin(omin, o);
+      omax = fmax(omax, o);
+    } else {
+      bad = true;
+    }
+  }
+  if (bad) atomicOr(&cnt->err, side_b ? 2u : 1u);
   // wave, then block reductions: one atomic per block and bound
   for (int off = 32; off > 0; off >>= 1) {
     dmin = fmin(dmin, __shfl_xor(dmin, off));
@@ -231,59 +250,79 @@ __device__ inline uint32_t job_bin(const JobGeom& G, double ra) {
 
 // keys for one side; tiles never cross jobs (tile table built on the host).
 // Entry positions are job-packed; values are the caller's global indices.
-__global__ __launch_bounds__(256) void k_batch_keygen(const BatchTile* __restrict__ tiles,
-                                                      uint32_t ntiles, const JobGeom* __restrict__ geo,
-                                                      const double* __restrict__ ra,
-                                                      const double* __restrict__ dec, int32_t lb_bits,
-                                                      int halo, uint32_t n_total,
-                                                      uint32_t* __restrict__ keys,
-                                                      uint32_t* __restrict__ vals, Counters* cnt) {
+__global__ __launch_bounds__(FT) void k_batch_keygen(const BatchTile* __restrict__ tiles,
+                                                     uint32_t ntiles, const JobGeom* __restrict__ geo,
+                                                     const double* __restrict__ ra,
+                                                     const double* __restrict__ dec, int32_t lb_bits,
+                                                     int halo, uint32_t n_total,
+                                                     uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals, Counters* cnt) {
   if (blockIdx.x >= ntiles) return;
   const BatchTile T = tiles[blockIdx.x];
-  const JobGeom G = geo[T.job];
-  const bool in = threadIdx.x < T.count;
-  const uint32_t src = T.src + threadIdx.x;
-  double a = 0.0, d = G.d0;
-  if (in) {
-    a = ra[src];
-    d = dec[src];
+  double av[TI], dv[TI];
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    const uint32_t k = j * FT + threadIdx.x;
+    av[j] = 0.0;
+    dv[j] = 0.0;
+    if (k < T.count) {
+      av[j] = ra[T.src + k];
+      dv[j] = dec[T.src + k];
+    }
   }
-  const bool ok = in && valid_pos(a, d);
-  if (!ok) { a = 0.0; d = G.d0; }
+  const JobGeom G = geo[T.job];
   const uint32_t jb = (uint32_t)T.job << lb_bits;
-  const int32_t z = job_zone(G, d);
-  const uint32_t b = job_bin(G, a);
-  if (in) {
-    keys[T.entry + threadIdx.x] = jb | ((uint32_t)z << G.rb) | b;
-    vals[T.entry + threadIdx.x] = src;
+  uint32_t hkey[TI];
+  uint64_t hm[TI];
+  uint32_t wave_n = 0;
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    const uint32_t k = j * FT + threadIdx.x;
+    const bool in = k < T.count;
+    const bool ok = in && valid_pos(av[j], dv[j]);
+    const double a = ok ? av[j] : 0.0, d = ok ? dv[j] : G.d0;
+    const int32_t z = job_zone(G, d);
+    const uint32_t b = job_bin(G, a);
+    if (in) {
+      keys[T.entry + k] = jb | ((uint32_t)z << G.rb) | b;
+      vals[T.entry + k] = T.src + k;
+    }
+    hm[j] = 0;
+    hkey[j] = 0;
+    if (halo) {
+      const int32_t zl = job_zone(G, d - G.rpad_deg), zh = job_zone(G, d + G.rpad_deg);
+      const int32_t other = (zl != z) ? zl : zh;
+      hkey[j] = jb | ((uint32_t)other << G.rb) | b;
+      hm[j] = __ballot(ok && other != z);
+      wave_n += (uint32_t)__popcll(hm[j]);
+    }
   }
   if (!halo) return;
-  const int32_t zl = job_zone(G, d - G.rpad_deg), zh = job_zone(G, d + G.rpad_deg);
-  const int32_t other = (zl != z) ? zl : zh;
-  const bool need = ok && other != z;
   // the block's halo copies placed with one atomic on the shared counter
   // (one per wave serialised every wave of the batch on one address)
-  __shared__ uint32_t s_wc[4];
-  __shared__ unsigned long long s_base[4];
-  const uint64_t m = __ballot(need);
+  __shared__ uint32_t s_wc[FT / 64];
+  __shared__ unsigned long long s_base[FT / 64];
   const uint32_t w = threadIdx.x >> 6;
-  if (lane_id() == 0) s_wc[w] = (uint32_t)__popcll(m);
+  if (lane_id() == 0) s_wc[w] = wave_n;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t nw = (blockDim.x + 63u) >> 6;
     unsigned long long tot = 0;
-    for (uint32_t u = 0; u < nw; ++u) tot += s_wc[u];
+    for (uint32_t u = 0; u < FT / 64; ++u) tot += s_wc[u];
     unsigned long long base = tot ? atomicAdd(&cnt->n_halo, tot) : 0ull;
-    for (uint32_t u = 0; u < nw; ++u) {
+    for (uint32_t u = 0; u < FT / 64; ++u) {
       s_base[u] = base;
       base += s_wc[u];
     }
   }
   __syncthreads();
-  if (need) {
-    const uint64_t pos = (uint64_t)n_total + s_base[w] + rank_in(m);
-    keys[pos] = jb | ((uint32_t)other << G.rb) | b;
-    vals[pos] = src | HALO_BIT;
+  uint64_t pos = (uint64_t)n_total + s_base[w];
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    if ((hm[j] >> lane_id()) & 1ull) {
+      keys[pos + rank_in(hm[j])] = hkey[j];
+      vals[pos + rank_in(hm[j])] = (T.src + j * FT + threadIdx.x) | HALO_BIT;
+    }
+    pos += (uint64_t)__popcll(hm[j]);
   }
 }
 
@@ -722,7 +761,7 @@ void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, const JobGeom*
                          const double* dec, int32_t lb_bits, bool halo, uint32_t n_total, uint32_t* keys,
                          uint32_t* vals, Counters* cnt, hipStream_t s) {
   if (ntiles == 0) return;
-  k_batch_keygen<<<ntiles, 256, 0, s>>>(tiles, ntiles, geo, ra, dec, lb_bits, halo ? 1 : 0, n_total, keys,
+  k_batch_keygen<<<ntiles, FT, 0, s>>>(tiles, ntiles, geo, ra, dec, lb_bits, halo ? 1 : 0, n_total, keys,
                                         vals, cnt);
 }
 

@@ -231,7 +231,8 @@ struct BatchJob {          // one job as given by the caller, plus host-derived 
   uint32_t a_entry, b_entry;  // first packed entry of the job in the A / B key arrays
   uint32_t zoff, zcap;     // the job's slice of the per-(job, zone) tables; zone budget
 };
-struct BatchTile {         // <= 256 consecutive sources of one job and one side
+constexpr int BATCH_TILE = 1024;  // sources per tile: 256 threads, four each
+struct BatchTile {         // <= BATCH_TILE consecutive sources of one job and one side
   uint32_t job, entry, src, count;
 };
 struct JobGeom {           // the job's local frame (computed on the device)

@@ -303,15 +303,35 @@ def hlc_xmatch_batch(jobs, a_ra, a_dec, b_ra, b_dec, out_pairs, out_sep, job_pai
     optional int64 device tensor of len(jobs). Returns (status, n_pairs).
     """
     _check_coords(a_ra, a_dec, b_ra, b_dec)
-    arr = (hlc_job * max(1, len(jobs)))()
-    for k, (ao, na, bo, nb, r) in enumerate(jobs):
-        arr[k].a_off, arr[k].na, arr[k].b_off, arr[k].nb, arr[k].r_arcsec = int(ao), int(na), int(bo), int(nb), float(r)
+    tab = job_table(jobs)
     if capacity is None:
         capacity = 0 if out_pairs is None else out_pairs.shape[0]
     o, n, tu = make_opts(precision, capacity, stream, flags, tuning)
-    st = load().hlc_xmatch_batch(arr, len(jobs), _ptr(a_ra), _ptr(a_dec), _ptr(b_ra), _ptr(b_dec),
-                                 _ptr(out_pairs), _ptr(out_sep), _ptr(job_pair_count), C.byref(o))
+    st = load().hlc_xmatch_batch(tab.ctypes.data_as(C.POINTER(hlc_job)), len(tab), _ptr(a_ra), _ptr(a_dec),
+                                 _ptr(b_ra), _ptr(b_dec), _ptr(out_pairs), _ptr(out_sep), _ptr(job_pair_count),
+                                 C.byref(o))
     return st, n.value
+
+
+# numpy layout of hlc_job (five 8-byte fields, no padding)
+JOB_DTYPE = None
+
+
+def job_table(jobs):
+    """The jobs as a contiguous numpy array laid out as hlc_job.
+
+    jobs: such an array (returned as is), or a sequence of
+    (a_off, na, b_off, nb, r_arcsec). A caller that repeats a batch can build
+    the table once and pass it on every call.
+    """
+    import numpy as np
+    global JOB_DTYPE
+    if JOB_DTYPE is None:
+        JOB_DTYPE = np.dtype([(name, "<i8" if ct is C.c_int64 else "<f8") for name, ct in hlc_job._fields_])
+        assert JOB_DTYPE.itemsize == C.sizeof(hlc_job)
+    if isinstance(jobs, np.ndarray) and jobs.dtype == JOB_DTYPE and jobs.flags.c_contiguous:
+        return jobs
+    return np.array([tuple(j) for j in jobs], dtype=JOB_DTYPE) if len(jobs) else np.zeros(1, JOB_DTYPE)[:0]
 
 
 def transfer_model() -> dict:

@@ -975,6 +975,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       Side A, B;
       SortScratch sc;
       MatchWs w;
+      uint32_t* msplit = nullptr;
       Geom g{};
       set_radius(g, r_arcsec);
       g.rb = 0;  // keys are pixels: a candidate must share the A entry's pixel
@@ -984,6 +985,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
         carve_side(c, B, capB, true, true);
         carve_sort(c, sc, std::max(capA, capB));
         carve_match_ws(c, w, capA, g, caps, false);
+        msplit = c.take<uint32_t>(merge_splits_len(capA, capB));
       };
       Carve sz{nullptr};
       lay(sz);
@@ -1004,7 +1006,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
       launch_layout64(B.vals, B.cnt, b_ra, b_dec, B.r64, s);
       launch_radec_gather(A.vals, A.cnt, a_ra, a_dec, A.radec, s);
       launch_radec_gather(B.vals, B.cnt, b_ra, b_dec, B.radec, s);
-      launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, w.lb, s);
+      launch_merge_lb(A.keys, A.cnt, B.keys, B.cnt, msplit, w.lb, s);
       launch_equal_ranges(A.keys, A.cnt, w.lb, B.keys, B.cnt, w.ranges, s);
       const Thresholds th = thresholds(r_arcsec);
       MatchArgs ma{};
@@ -1298,7 +1300,9 @@ struct BatchState {  // per device
   BatchJob* d_jobs = nullptr;
   BatchTile *d_tA = nullptr, *d_tB = nullptr;
   hipStream_t st = nullptr;
+  hipStream_t st2 = nullptr;  // A's chain, beside B's
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t graph_key = 0;
@@ -1363,7 +1367,7 @@ void tune_save() {
 struct BatchBufs {
   unsigned long long* bounds;
   JobGeom* geo;
-  uint32_t *kA, *vA, *kB, *vB, *lb, *zstart, *ckey, *cval;
+  uint32_t *kA, *vA, *kB, *vB, *lb, *msplit, *zstart, *ckey, *cval;
   int32_t* zmarg;
   GroupRanges* ranges;
   Rec64 *rA64, *rB64;
@@ -1374,7 +1378,7 @@ struct BatchBufs {
   uint64_t band_cap;
   Regions reg;
   unsigned long long* jcount;
-  SortScratch sc;
+  SortScratch sc, scA;
 };
 
 void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Caps& caps, bool own_jcount) {
@@ -1387,7 +1391,8 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Ca
   b.vA = c.take<uint32_t>(NA);
   b.kB = c.take<uint32_t>(NB2);
   b.vB = c.take<uint32_t>(NB2);
-  carve_sort(c, b.sc, std::max(std::max(NA, NB2), ng));
+  carve_sort(c, b.sc, std::max(NB2, ng));
+  carve_sort(c, b.scA, NA);
   if (fp32) {
     b.rA32 = c.take<Rec32>(NA);
     b.rB32 = c.take<Rec32>(NB2);
@@ -1401,6 +1406,7 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Ca
     b.radecA = b.radecB = nullptr;
   }
   b.lb = c.take<uint32_t>(NA);
+  b.msplit = c.take<uint32_t>(merge_splits_len(NA, NB2));
   b.ranges = c.take<GroupRanges>(ng);
   b.ckey = c.take<uint32_t>(ng);
   b.cval = c.take<uint32_t>(ng);
@@ -1413,38 +1419,49 @@ void carve_batch(Carve& c, BatchBufs& b, const BatchPlan& P, bool fp32, const Ca
   b.jcount = own_jcount ? c.take<unsigned long long>(std::max(P.njobs, 1)) : nullptr;
 }
 
-// Every launch of one batched call, in order, on stream s (no host
-// synchronisation, so the sequence can be captured into a graph).
+// Every launch of one batched call on stream s, A's chain forked to BS.st2
+// and joined back (no host synchronisation, so the sequence can be captured
+// into a graph with two branches).
 void batch_enqueue(Device& dev, BatchState& BS, const BatchPlan& P, const BatchBufs& b, const double* a_ra,
                    const double* a_dec, const double* b_ra, const double* b_dec, hlc_pair* out_pairs,
                    double* out_sep, uint64_t cap, unsigned long long* jcount, double factor, bool fp32,
                    hipStream_t s) {
   const uint32_t NA = (uint32_t)P.NA, NB = (uint32_t)P.NB;
+  hipStream_t s2 = BS.st2;
+  auto fork = [&](int k) {
+    (void)hipEventRecord(BS.ev_fork[k], s);
+    (void)hipStreamWaitEvent(s2, BS.ev_fork[k], 0);
+  };
+  auto join = [&](int k) {
+    (void)hipEventRecord(BS.ev_join[k], s2);
+    (void)hipStreamWaitEvent(s, BS.ev_join[k], 0);
+  };
   launch_zero_counters(dev.cnt, s);
   launch_zero_u64(jcount, (uint32_t)P.njobs, s);
   launch_job_bounds_init(b.bounds, P.njobs, s);
+  fork(0);
   launch_job_bounds(BS.d_tA, (uint32_t)P.tA.size(), BS.d_jobs, a_ra, b_ra, a_ra, a_dec, false, b.bounds,
-                    dev.cnt, s);
+                    dev.cnt, s2);
   launch_job_bounds(BS.d_tB, (uint32_t)P.tB.size(), BS.d_jobs, a_ra, b_ra, b_ra, b_dec, true, b.bounds,
                     dev.cnt, s);
+  join(0);
   launch_job_frames(BS.d_jobs, P.njobs, a_ra, b_ra, b.bounds, P.lb_bits, factor, b.geo, s);
-  launch_batch_keygen(BS.d_tA, (uint32_t)P.tA.size(), b.geo, a_ra, a_dec, P.lb_bits, false, NA, b.kA, b.vA,
-                      dev.cnt, s);
-  launch_batch_keygen(BS.d_tB, (uint32_t)P.tB.size(), b.geo, b_ra, b_dec, P.lb_bits, true, NB, b.kB, b.vB,
-                      dev.cnt, s);
   const DevCount cA{NA, NA, nullptr};
   const DevCount cB{NB, 2 * NB, &dev.cnt->n_halo};
-  radix_sort(b.kA, b.vA, cA, 32, b.sc, s);
+  fork(1);
+  launch_batch_keygen(BS.d_tA, (uint32_t)P.tA.size(), b.geo, a_ra, a_dec, P.lb_bits, false, NA, b.kA, b.vA,
+                      dev.cnt, s2);
+  radix_sort(b.kA, b.vA, cA, 32, b.scA, s2);
+  if (fp32) launch_batch_layout32(b.kA, b.vA, cA, a_ra, a_dec, b.geo, P.lb_bits, b.rA32, b.radecA, s2);
+  else launch_layout64(b.vA, cA, a_ra, a_dec, b.rA64, s2);
+  launch_batch_keygen(BS.d_tB, (uint32_t)P.tB.size(), b.geo, b_ra, b_dec, P.lb_bits, true, NB, b.kB, b.vB,
+                      dev.cnt, s);
   radix_sort(b.kB, b.vB, cB, 32, b.sc, s);
-  if (fp32) {
-    launch_batch_layout32(b.kA, b.vA, cA, a_ra, a_dec, b.geo, P.lb_bits, b.rA32, b.radecA, s);
-    launch_batch_layout32(b.kB, b.vB, cB, b_ra, b_dec, b.geo, P.lb_bits, b.rB32, b.radecB, s);
-  } else {
-    launch_layout64(b.vA, cA, a_ra, a_dec, b.rA64, s);
-    launch_layout64(b.vB, cB, b_ra, b_dec, b.rB64, s);
-  }
+  if (fp32) launch_batch_layout32(b.kB, b.vB, cB, b_ra, b_dec, b.geo, P.lb_bits, b.rB32, b.radecB, s);
+  else launch_layout64(b.vB, cB, b_ra, b_dec, b.rB64, s);
   launch_batch_zone_tables(b.geo, P.njobs, BS.d_jobs, P.ztotal, P.lb_bits, b.kB, cB, b.zmarg, b.zstart, s);
-  launch_merge_lb(b.kA, cA, b.kB, cB, b.lb, s);
+  join(1);
+  launch_merge_lb(b.kA, cA, b.kB, cB, b.msplit, b.lb, s);
   launch_batch_ranges(b.kA, cA, b.lb, b.kB, b.geo, P.lb_bits, b.zmarg, b.zstart, b.ranges, b.ckey, b.cval, s);
   const uint32_t ng = (NA + GROUP - 1) / GROUP;
   radix_sort(b.ckey, b.cval, DevCount{ng, ng, nullptr}, 32, b.sc, s);
@@ -1515,6 +1532,11 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
   BatchState& BS = g_bstate[dev_id];
   if (!BS.st) {
     HLC_TRY(hipStreamCreate(&BS.st));
+    HLC_TRY(hipStreamCreateWithFlags(&BS.st2, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      HLC_TRY(hipEventCreateWithFlags(&BS.ev_fork[k], hipEventDisableTiming));
+      HLC_TRY(hipEventCreateWithFlags(&BS.ev_join[k], hipEventDisableTiming));
+    }
     HLC_TRY(hipEventCreateWithFlags(&BS.ev_in, hipEventDisableTiming));
     HLC_TRY(hipEventCreateWithFlags(&BS.ev_out, hipEventDisableTiming));
     HLC_TRY(hipEventCreate(&BS.ev_t0));
@@ -2126,7 +2148,9 @@ void hlc_shutdown(void) {
     drop_graph(B);
     if (B.tables) (void)hipFree(B.tables);
     if (B.st) (void)hipStreamDestroy(B.st);
-    for (hipEvent_t e : {B.ev_in, B.ev_out, B.ev_t0, B.ev_t1})
+    if (B.st2) (void)hipStreamDestroy(B.st2);
+    for (hipEvent_t e : {B.ev_in, B.ev_out, B.ev_t0, B.ev_t1, B.ev_fork[0], B.ev_fork[1], B.ev_join[0],
+                         B.ev_join[1]})
       if (e) (void)hipEventDestroy(e);
     B = BatchState();
   }

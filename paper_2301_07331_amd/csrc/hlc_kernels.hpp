@@ -58,8 +58,10 @@ void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, 
                      Rec64* rec, hipStream_t s);
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec32* rec, double2* radec, hipStream_t s);
+// lb[i] = number of B keys below keysA[i]; splits: merge_splits_len words of scratch
+size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap);
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
-                     const DevCount& nb, uint32_t* lb, hipStream_t s);
+                     const DevCount& nb, uint32_t* splits, uint32_t* lb, hipStream_t s);
 // idx[i] = first position of the sorted keys with key >= i << shift, i < T
 void launch_key_index(const uint32_t* keys, const DevCount& n, int shift, uint32_t T, uint32_t* idx,
                       hipStream_t s);

@@ -484,20 +484,30 @@ __device__ inline uint32_t merge_split(const uint32_t* A, uint32_t na, const uin
   return lo;
 }
 
+// The split of every tile boundary, all searches in parallel (one thread
+// each), so that no merge tile waits on a search through the whole arrays.
+__global__ __launch_bounds__(256) void k_merge_splits(const uint32_t* __restrict__ A, DevCount nac,
+                                                      const uint32_t* __restrict__ B, DevCount nbc,
+                                                      uint32_t nsplit, uint32_t* __restrict__ splits) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsplit) return;
+  const uint32_t na = nac.get(), nb = nbc.get();
+  const uint64_t d = min((uint64_t)t * MP_TILE, (uint64_t)na + nb);
+  splits[t] = merge_split(A, na, B, nb, (uint32_t)d);
+}
+
 __global__ __launch_bounds__(MP_THREADS) void k_merge_lb(const uint32_t* __restrict__ A, DevCount nac,
                                                          const uint32_t* __restrict__ B, DevCount nbc,
+                                                         const uint32_t* __restrict__ splits,
                                                          uint32_t* __restrict__ lb) {
   __shared__ uint32_t sA[MP_TILE];
   __shared__ uint32_t sB[MP_TILE];
-  __shared__ uint32_t s_split[2];
   const uint32_t na = nac.get(), nb = nbc.get();
   const uint64_t total = (uint64_t)na + nb;
   const uint32_t d0 = blockIdx.x * MP_TILE;
   if ((uint64_t)d0 >= total) return;  // beyond the device-side counts (block-uniform)
   const uint32_t d1 = (uint32_t)min((uint64_t)d0 + MP_TILE, total);
-  if (threadIdx.x < 2) s_split[threadIdx.x] = merge_split(A, na, B, nb, threadIdx.x == 0 ? d0 : d1);
-  __syncthreads();
-  const uint32_t i0 = s_split[0], i1 = s_split[1];
+  const uint32_t i0 = splits[blockIdx.x], i1 = splits[blockIdx.x + 1];
   const uint32_t j0 = d0 - i0, j1 = d1 - i1;
   const uint32_t la = i1 - i0, lb_ = j1 - j0;
   for (uint32_t k = threadIdx.x; k < la; k += MP_THREADS) sA[k] = A[i0 + k];
@@ -1049,11 +1059,14 @@ void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, 
   k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec, radec);
 }
 
+size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap) { return (size_t)cdiv(na_cap + nb_cap, MP_TILE) + 1; }
+
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
-                     const DevCount& nb, uint32_t* lb, hipStream_t s) {
+                     const DevCount& nb, uint32_t* splits, uint32_t* lb, hipStream_t s) {
   if (na.cap == 0) return;
-  uint32_t blocks = cdiv((uint64_t)na.cap + nb.cap, MP_TILE);
-  k_merge_lb<<<blocks, MP_THREADS, 0, s>>>(keysA, na, keysB, nb, lb);
+  const uint32_t blocks = cdiv((uint64_t)na.cap + nb.cap, MP_TILE);
+  k_merge_splits<<<cdiv(blocks + 1, 256), 256, 0, s>>>(keysA, na, keysB, nb, blocks + 1, splits);
+  k_merge_lb<<<blocks, MP_THREADS, 0, s>>>(keysA, na, keysB, nb, splits, lb);
 }
 
 void launch_key_index(const uint32_t* keys, const DevCount& n, int shift, uint32_t T, uint32_t* idx,

@@ -93,3 +93,20 @@ def test_binding_refuses_cpu_tensors():
     x = torch.zeros(4, dtype=torch.float64)
     with pytest.raises(ValueError):
         hlc.hlc_xmatch(x, x, x, x, 1.0, None, None)
+
+
+def test_job_table_layout_matches_hlc_job():
+    """The numpy job table the batched binding passes is byte-for-byte hlc_job."""
+    import numpy as np
+    import paper_2301_07331_amd as hlc
+    jobs = [(0, 10, 5, 20, 1.5), (10, 0, 25, 3, 0.25), ((1 << 31) - 2, 1, 0, 1, 3600.0)]
+    t = hlc.job_table(jobs)
+    assert t.dtype.itemsize == C.sizeof(hlc.hlc_job) and t.flags.c_contiguous and len(t) == 3
+    for name, _ in hlc.hlc_job._fields_:
+        assert t.dtype.fields[name][1] == getattr(hlc.hlc_job, name).offset
+    arr = (hlc.hlc_job * 3).from_buffer_copy(t.tobytes())
+    for k, (ao, na, bo, nb, r) in enumerate(jobs):
+        assert (arr[k].a_off, arr[k].na, arr[k].b_off, arr[k].nb, arr[k].r_arcsec) == (ao, na, bo, nb, r)
+    assert hlc.job_table(t) is t  # a prebuilt table is passed as is
+    assert len(hlc.job_table([])) == 0
+    assert np.array_equal(hlc.job_table(list(t)), t)

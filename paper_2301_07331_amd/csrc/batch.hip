@@ -334,8 +334,12 @@ __global__ __launch_bounds__(256) void k_batch_layout32(const uint32_t* __restri
                                                         const JobGeom* __restrict__ geo, int32_t lb_bits,
                                                         Rec32* __restrict__ rec,
                                                         double2* __restrict__ radec) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nc.get()) return;
+  // XCD-aware over the blocks the device-side count fills (the grid covers the
+  // capacity): a job's sources, read in its sorted order, land in one L2
+  const uint32_t n = nc.get(), nb = (n + blockDim.x - 1) / blockDim.x;
+  if (blockIdx.x >= nb) return;
+  const uint32_t p = xcd_block(blockIdx.x, nb) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
   const uint32_t v = vals[p], i = v & IDX_MASK;
   const JobGeom& G = geo[keys[p] >> lb_bits];
   const double a = ra[i], d = dec[i];

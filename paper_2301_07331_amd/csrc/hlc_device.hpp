@@ -97,6 +97,14 @@ struct SrcRec32 {   // per-source FP32 record with its FP64 position (32 B)
   double ra, dec;
 };
 
+// Logical block of a dispatched block such that consecutive logical blocks
+// run on the same XCD (blocks are dispatched round-robin over the 8 XCDs, each
+// with its own L2): neighbouring tiles then share that L2.
+__device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
+  const uint32_t q = nblocks >> 3, r = nblocks & 7u, x = bid & 7u, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Geometry helpers (identical code for A and B keys, so they are monotone).
 // ---------------------------------------------------------------------------

@@ -55,12 +55,6 @@ constexpr int WAVES = MT / 64;
 constexpr int QCAP = 256;   // per-wave candidate queue, staged above QCAP - 64
 constexpr unsigned long long CAND_BLOCKS_MAX = 8192;  // grid cap of the certification walk
 
-__device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
-  // consecutive logical blocks on the same XCD (dispatch is round-robin over 8)
-  uint32_t q = nblocks >> 3, r = nblocks & 7u, x = bid & 7u, k = bid >> 3;
-  return x * q + min(x, r) + k;
-}
-
 // Thresholds of the eq. (4) radius of one pair (arcsec): chord^2 bounds of
 // the FP64 filter and the haversine band. r carries <= 3u from the sqrt and
 // products and the degree sine <= 3u, so 32u margins hold.

@@ -398,8 +398,12 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
                                                   Rec64* __restrict__ rec) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nc.get()) return;
+  // XCD-aware over the blocks the device-side count fills (the grid covers the
+  // capacity): the sources a run of sorted entries reads land in one L2
+  const uint32_t n = nc.get(), nb = (n + blockDim.x - 1) / blockDim.x;
+  if (blockIdx.x >= nb) return;
+  const uint32_t p = xcd_block(blockIdx.x, nb) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
   uint32_t v = vals[p];
   uint32_t i = v & IDX_MASK;
   double x, y, z;

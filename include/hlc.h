@@ -20,7 +20,8 @@
  *   - The pair set is exact: a pair is reported iff its exact separation is
  *     <= r_arcsec/3600 degrees, where pairs within a relative 1e-28 of r
  *     (indistinguishable at double-double precision) count as matches.
- *   - r_arcsec must lie in (0, 3600]; 0 <= na, nb < 2^31.
+ *   - r_arcsec must lie in (0, 3600]; 0 <= na, nb <= 2^31 - 2^16 (B's
+ *     entries, halo copies included, then stay below 2^32).
  *   - A and B may be the same arrays; they are still two catalogues, so
  *     (i, i) is reported with separation 0, unless HLC_SELF is set.
  *

@@ -352,10 +352,14 @@ int check_opts(const hlc_opts* o) {
   return HLC_OK;
 }
 
+// Largest catalogue: B's entries (sources plus halo copies, up to twice the
+// sources) and every grid rounded up to whole tiles stay below 2^32.
+constexpr int64_t MAX_SOURCES = (int64_t(1) << 31) - (int64_t(1) << 16);
+
 int check_common(double r_arcsec, int64_t na, int64_t nb, const hlc_opts* o) {
   HLC_CHECK(check_opts(o));
   if (!(r_arcsec > 0.0) || !(r_arcsec <= 3600.0)) return HLC_E_INVAL;
-  if (na < 0 || nb < 0 || na >= (int64_t(1) << 31) || nb >= (int64_t(1) << 31)) return HLC_E_INVAL;
+  if (na < 0 || nb < 0 || na > MAX_SOURCES || nb > MAX_SOURCES) return HLC_E_INVAL;
   return HLC_OK;
 }
 
@@ -1062,7 +1066,7 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
   *out = nullptr;
   if (!opts) return HLC_E_INVAL;
   if (!(r_arcsec > 0.0) || !(r_arcsec <= 3600.0)) return HLC_E_INVAL;
-  if (n < 0 || n >= (int64_t(1) << 31)) return HLC_E_INVAL;
+  if (n < 0 || n > MAX_SOURCES) return HLC_E_INVAL;
   if (n > 0 && (!ra_deg || !dec_deg)) return HLC_E_INVAL;
   try {
     Device* dev = nullptr;

@@ -67,7 +67,8 @@ def test_argument_errors_are_caught_before_any_device_call(lib):
     assert lib.hlc_xmatch(fake, fake, 1, fake, fake, 1, 1.0, fake, fake, None) == hlc.HLC_E_INVAL
     for r in (0.0, -1.0, float("nan"), 3600.001, float("inf")):
         assert lib.hlc_xmatch(fake, fake, 1, fake, fake, 1, r, fake, fake, C.byref(o)) == hlc.HLC_E_INVAL
-    for na, nb in ((-1, 1), (1, -1), (1 << 31, 1), (1, 1 << 31)):
+    big = (1 << 31) - (1 << 16) + 1  # one above the largest catalogue
+    for na, nb in ((-1, 1), (1, -1), (1 << 31, 1), (1, 1 << 31), (big, 1), (1, big)):
         assert lib.hlc_xmatch(fake, fake, na, fake, fake, nb, 1.0, fake, fake, C.byref(o)) == hlc.HLC_E_INVAL
     o.capacity = -5
     assert lib.hlc_xmatch(fake, fake, 1, fake, fake, 1, 1.0, fake, fake, C.byref(o)) == hlc.HLC_E_INVAL

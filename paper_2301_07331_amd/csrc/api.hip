@@ -564,6 +564,9 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   launch_key_index(B.keys, B.cnt, ki.shift, ki.T, w.kidx, ps);
   launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, ps);
   if (prof) (void)hipEventRecord(dev.ev[8], ps);
+  // the candidate regions are cleared before the join, beside the ranges
+  const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
+  launch_regions_reset(oa, s);
   if (ps != s) {
     (void)hipEventRecord(dev.prepped, ps);
     (void)hipStreamWaitEvent(s, dev.prepped, 0);
@@ -597,8 +600,6 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.b_err = rad.b_err;
   ma.k_sigma = rad.k;
   ma.hp_order = -1;
-  const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
-  launch_regions_reset(oa, s);
   launch_filter(ma, oa, fp32, filter_items, s);
   if (prof) (void)hipEventRecord(dev.ev[9], s);
   launch_cand(ma, oa, fp32, s);
@@ -770,11 +771,14 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     if (!keep_a) partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, s);
     HLC_TRY(hipEventRecord(dev->fork, s));
     HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
-    HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
   } else {
     mark(*dev, slA.keygen, s);
   }
-  HLC_CHECK(partition(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s, dev->bsorted));
+  // B's keygen queued before A's sort launches, so that it follows A's keygen
+  // on the device without waiting for the host to launch A's radix passes
+  partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
+  if (!self) HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
+  HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, sc, B, slB, s, dev->bsorted));
   if (self) {
     // one partition serves both roles; its halo copies are skipped as A
     for (int k : {slA.sort, slA.layout}) mark(*dev, k, s);

@@ -108,7 +108,8 @@ def parse():
                    help="also run a plain device copy of known size (for HBM counter scaling)")
     p.add_argument("--forms", default="xmatch,batch,quad",
                    help="xmatch (the headline, always run), batch (10,000 jobs), quad (paper-scheme "
-                        "emulation), stream (400M x 100M from pinned host memory; not in the default set)")
+                        "emulation), stream (400M x 100M from pinned host memory) and stress (20M x 20M "
+                        "precision stress at r = 0.5, 1, 5 arcsec); the last two are not in the default set")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="print the filter kernel's HBM traffic from two rocprofv3 --pmc output folders and exit")
     return p.parse_args()
@@ -218,6 +219,51 @@ def bench_stream(hlc, torch):
         print(f"[bench] stream {name}: {sec:.2f} s, {n} pairs", file=sys.stderr, flush=True)
     res["workload"] = f"{name_w}: {na} A x {nb} B in pinned host memory, r={r} arcsec"
     res["transfer_model"] = hlc.transfer_model()
+    return res
+
+
+def bench_stress(hlc, torch, dev, steps, warmup):
+    """The precision-stress workload at full size (20M x 20M, 10,000 clumps,
+    counterparts on [0.99 r, 1.01 r]) for r = 0.5, 1, 5 arcsec: FP32 + FP64
+    recheck against plain FP64, the plain call's geometry."""
+    import synth
+    res = {}
+    for r in (0.5, 1.0, 5.0):
+        t0 = time.time()
+        c = synth.stress_pair(r)
+        print(f"[bench] generated {c.name} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        arrs = [torch.from_numpy(x).to(dev) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+        out = sep = None
+        cap = 0
+        row = {}
+        for name, prec in (("fp32", hlc.HLC_FP32_RECHECK), ("fp64", hlc.HLC_FP64)):
+            for k in range(max(1, warmup) + 1):
+                st, n = hlc.hlc_xmatch(*arrs, r, out, sep, precision=prec, capacity=cap)
+                if st == hlc.HLC_E_OVERFLOW or (st == hlc.HLC_OK and cap == 0 and n > 0):
+                    cap = n + 1024
+                    out = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+                    sep = torch.empty(cap, dtype=torch.float64, device=dev)
+                elif st != hlc.HLC_OK:
+                    raise hlc.HLCError(st, f"stress r={r}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(max(1, min(steps, 5))):
+                st, n = hlc.hlc_xmatch(*arrs, r, out, sep, precision=prec, capacity=cap)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / max(1, min(steps, 5)) * 1e3
+            if st != hlc.HLC_OK:
+                raise hlc.HLCError(st, f"stress r={r}")
+            s = hlc.last_stats()
+            row[name] = {"ms_per_call": ms, "a_sources_per_s": c.na / (ms * 1e-3), "pairs": int(n),
+                         "candidates": int(s["n_candidates"]), "band": int(s["n_band"])}
+            print(f"[bench] stress r={r} {name}: {ms:.2f} ms, {n} pairs, {s['n_candidates']} candidates",
+                  file=sys.stderr, flush=True)
+        if row["fp32"]["pairs"] != row["fp64"]["pairs"]:
+            raise RuntimeError(f"stress r={r}: FP32 and FP64 forms disagree on the pair count")
+        res[f"r{r:g}"] = row
+        del arrs, out, sep
+        torch.cuda.empty_cache()
+    res["workload"] = "stress 20000000x20000000, 10000 clumps (sigma 30 arcsec), counterparts on [0.99 r, 1.01 r]"
     return res
 
 
@@ -336,9 +382,11 @@ def main():
     extra = {}
     if "quad" in forms:
         extra["quad_direction"] = bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, head["n_pairs"])
-    if "batch" in forms or "stream" in forms:
+    if "batch" in forms or "stream" in forms or "stress" in forms:
         del a_ra, a_dec, b_ra, b_dec, out, sep
         torch.cuda.empty_cache()
+    if "stress" in forms:
+        extra["stress"] = bench_stress(hlc, torch, dev, args.steps, args.warmup)
     if "batch" in forms:
         extra["batch"] = bench_batch(hlc, torch, dev, args.steps, args.warmup)
     if "stream" in forms:

@@ -24,7 +24,7 @@ EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition",
 class hlc_tuning(C.Structure):
     _fields_ = [("zone_height_arcsec", C.c_double), ("ra_bins_log2", C.c_int32),
                 ("filter_items", C.c_int32), ("zone_height_factor", C.c_double),
-                ("reserved", C.c_int32 * 4)]
+                ("fraction_sort", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class hlc_opts(C.Structure):
@@ -145,6 +145,7 @@ def make_opts(precision=HLC_FP32_RECHECK, capacity=0, stream=None, flags=0, tuni
         tu.ra_bins_log2 = int(tuning.get("ra_bins_log2", 0))
         tu.filter_items = int(tuning.get("filter_items", 0))
         tu.zone_height_factor = float(tuning.get("zone_height_factor", 0.0))
+        tu.fraction_sort = int(tuning.get("fraction_sort", 0))
         o.tuning = C.pointer(tu)
     return o, n, tu
 

@@ -228,6 +228,7 @@ Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits
   g.bin_scale = (double)g.nbins / span;
   // spare low key bits carry the RA position inside the bin
   g.fb = std::min(8, std::max(0, 32 - zb - g.rb));
+  g.frac_sorted = 0;
   return g;
 }
 
@@ -367,6 +368,9 @@ double tuned_height(const hlc_opts* o) {
   return (o->tuning && o->tuning->zone_height_arcsec > 0) ? o->tuning->zone_height_arcsec : 0.0;
 }
 int tuned_bins(const hlc_opts* o) { return o->tuning ? o->tuning->ra_bins_log2 : 0; }
+bool tuned_fraction_sort(const hlc_opts* o) { return o->tuning && o->tuning->fraction_sort == 1; }
+// lowest key bit the radix sort orders: 0 when the sub-bin bits are sorted too
+int sort_lo(const Geom& g) { return g.frac_sorted ? 0 : g.fb; }
 int tuned_items(const hlc_opts* o) { return (o->tuning && o->tuning->filter_items > 0) ? o->tuning->filter_items : 1; }
 
 // One partitioned catalogue.
@@ -408,7 +412,7 @@ void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n
   sd.ra = ra;
   sd.dec = dec;
   // an odd number of radix passes ends in the scratch pair unless it starts there
-  const bool from_alt = (radix_passes(key_bits(g), g.fb) & 1) != 0;
+  const bool from_alt = (radix_passes(key_bits(g), sort_lo(g)) & 1) != 0;
   uint32_t* kk = from_alt ? sc.keys_alt : sd.keys;
   uint32_t* vv = from_alt ? sc.vals_alt : sd.vals;
   launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
@@ -421,9 +425,9 @@ void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n
 int partition_sort(Device& dev, const Geom& g, bool l64, bool l32, const SortScratch& sc, Side& sd,
                    const Slots& sl, hipStream_t s, hipEvent_t sorted_ev = nullptr) {
   const int bits = key_bits(g);
-  const bool from_alt = (radix_passes(bits, g.fb) & 1) != 0;
+  const bool from_alt = (radix_passes(bits, sort_lo(g)) & 1) != 0;
   mark(dev, sl.sort_begin, s);
-  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, g.fb);
+  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, sort_lo(g));
   mark(dev, sl.sort, s);
   if (sorted_ev) HLC_TRY(hipEventRecord(sorted_ev, s));
   if (l64 && sd.r64) {
@@ -457,7 +461,7 @@ struct KeyIndex {
 // multiples of 2^fb)
 KeyIndex key_index_dims(const Geom& g) {
   const int kb = key_bits(g);
-  const int shift = std::max(std::max(6, kb - 18), g.fb);
+  const int shift = std::max(std::max(6, kb - 18), sort_lo(g));
   return KeyIndex{shift, (uint32_t)((1ull << std::max(kb - shift, 0)) + 1)};
 }
 
@@ -716,6 +720,9 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   const Slots slA = prof ? Slots{5, -1, 6, 7} : NO_SLOTS;
 
   Geom g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), Frame{});
+  // (set before A's speculative keygen: the number of radix passes decides
+  // which buffer that keygen writes)
+  g.frac_sorted = tuned_fraction_sort(o) ? 1 : 0;
   Side A, B;
   SortScratch sc, scA;
   MatchWs w;
@@ -752,6 +759,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   dev->last_full = is_full(f);
   const bool keep_a = spec && dev->last_full;
   g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
+  g.frac_sorted = tuned_fraction_sort(o) ? 1 : 0;
   Carve sizing{nullptr};
   lay(sizing);
   HLC_CHECK(ensure_ws(*dev, sizing.off + 256));

@@ -42,6 +42,8 @@ struct Geom {
   uint32_t nbins;
   int32_t fb;         // RA sub-bin bits carried in the low key bits (0..8)
   int32_t full_ra;    // the bins cover RA [0, 360): windows wrap at the seam
+  int32_t frac_sorted;  // the sort also orders the sub-bin bits: B windows
+                        // are searched at sub-bin resolution
 };
 
 // An entry count known on the host (base) plus an optional count that only

@@ -657,6 +657,10 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     const int64_t bf = key_bin(g, k[q]), bl = key_bin(g, k[qe]);
     const int32_t m = zmarg[z];
     int64_t lo = bf - m, hi = bl + m;
+    // sub-bin positions of the window's edges (searched only when B's keys
+    // are sorted on their sub-bin bits as well)
+    const uint32_t cell_top = (1u << g.fb) - 1u;
+    uint32_t flo = 0u, fhi = cell_top;
     if (m >= 0) {
       // the window from the bin edges of the segment's first and last
       // sources: bf * width is exact (width = 360 / 2^rb), bin_of is
@@ -684,22 +688,33 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
         lo = (int64_t)bin_of(g, x);
         hi = (int64_t)bin_of(g, y);
       }
+      if (g.frac_sorted) {
+        // the key is monotone in RA within a zone, so every B entry of RA in
+        // [x, y] lies between the keys of the two edges (taken in the bin
+        // each edge falls in, after the wrap at the seam)
+        const double xe = (g.full_ra && x < 0.0) ? x + 360.0 : x;
+        const double ye = (g.full_ra && y >= 360.0) ? y - 360.0 : y;
+        flo = frac_of(g, xe, bin_of(g, xe));
+        fhi = frac_of(g, ye, bin_of(g, ye));
+      }
     }
     if (m < 0 || hi - lo + 1 >= nbins) {
       L.add(zs, ze);
     } else if (zs < ze) {
       auto lower = [&](uint64_t K) { return index_lower(keysB, kidx, kshift, kT, K, zs, ze); };
-      uint32_t s = lower(make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)));
-      // (the end of a cell: its last key + 1 = the first key of the next)
+      uint32_t s = lower((uint64_t)make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)) + (lo < 0 ? 0u : flo));
+      // (the end of a cell: its last key + 1 = the first key of the next;
+      // with sorted sub-bin bits, the edge's own key + 1)
       const uint64_t cell = 1ull << g.fb;
-      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) + cell);
+      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) +
+                         (hi > nbins - 1 ? cell : (uint64_t)fhi + 1u));
       if (hi > nbins - 1) {  // window passes RA 360: low bins of the zone
-        uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + cell);
+        uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + (uint64_t)fhi + 1u);
         L.add(zs, e2);
       }
       L.add(s, e);
       if (lo < 0) {  // window passes RA 0: high bins of the zone
-        uint32_t s2 = lower(make_key(g, z, (uint32_t)(nbins + lo)));
+        uint32_t s2 = lower((uint64_t)make_key(g, z, (uint32_t)(nbins + lo)) + flo);
         L.add(s2, ze);
       }
     }

@@ -523,3 +523,33 @@ def test_frame_transitions(hlc, prec):
         (a, b) = cases[k]
         keys, sep = gpu_xmatch(a[0], a[1], b[0], b[1], 2.0, prec)
         assert_same(keys, sep, refs[k], label=k)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_fraction_sort(hlc, prec):
+    """fraction_sort = 1: the sub-bin key bits sorted too and B's windows cut at
+    sub-bin resolution, on the adversarial kinds, tuned geometries (fine and
+    coarse bins, thin and wide zones), the framed footprints and clumps."""
+    fs = {"fraction_sort": 1}
+    for kind in KINDS:
+        for seed, r in ((0, 0.5), (1, 2.0), (2, 7.0)):
+            a_ra, a_dec, b_ra, b_dec = synth.adversarial(kind, 2999, seed, r)
+            ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+            keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec, tuning=fs)
+            assert_same(keys, sep, ref, label=f"fraction_sort {kind} seed={seed} r={r}")
+    a_ra, a_dec, b_ra, b_dec = synth.adversarial("dense", 3001, 5, 2.0)
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, 2.0)
+    for zh in (4.01, 30.0, 3600.0 * 4):
+        for bins in (0, 1, 6, 14, 24):
+            tun = dict(fs, zone_height_arcsec=zh, ra_bins_log2=bins)
+            keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, 2.0, prec, tuning=tun)
+            assert_same(keys, sep, ref, label=f"fraction_sort zh={zh} bins={bins}")
+    for name, a_ra, a_dec, b_ra, b_dec, r in _framed_cases():
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec, tuning=fs)
+        assert_same(keys, sep, ref, label=f"fraction_sort {name}")
+    c = synth.stress_pair(1.0, n=2_000_000, n_clumps=1000)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 1.0)
+    keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 1.0, prec, tuning=fs)
+    assert_same(keys, sep, ref, label="fraction_sort stress 2M")
+    _print("fraction_sort stress 2M", hlc.last_stats())

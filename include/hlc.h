@@ -85,9 +85,10 @@ typedef struct hlc_tuning {
                               * the filter kernel (0 = one)                    */
   double zone_height_factor; /* batched form: scale of each job's density-     *
                               * derived zone height (0 = autotuned and cached)  */
-  int32_t fraction_sort;     /* 1: the partition also sorts the RA sub-bin     *
-                              * bits (one more radix pass; narrower windows    *
-                              * inside dense clumps); 0: not                   */
+  int32_t fraction_sort;     /* hlc_xmatch, hlc_xmatch_radii: 1 = the          *
+                              * partition also sorts the RA sub-bin bits (one  *
+                              * more radix pass; narrower windows inside dense *
+                              * clumps); 0 = not                               */
   int32_t reserved[3];
 } hlc_tuning;
 

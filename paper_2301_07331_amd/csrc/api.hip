@@ -202,10 +202,41 @@ Geom make_geom(double r_arcsec, double h_as, int64_t na, int64_t nb, int ra_bits
   h = std::max(h, 2.0001 * g.rpad_deg);
   h = std::max(h, dspan / 65536.0);
   int64_t nz = std::max<int64_t>(1, (int64_t)std::ceil(dspan / h));
+  g.dec0 = f.dec_lo;
+  g.dec_s = f.dec_lo;
+  g.dec_n = f.dec_hi;
+  g.nzs = g.nzn = 0;
+  // Polar cap bands: a zone that reaches a pole is scanned as a whole ring,
+  // so within 1 deg of a pole the zones are about 16 r high (at least
+  // 2.0001 r padded, at most 4096 per band); the zones between keep height
+  // h, widened to a whole number of zones.
+  const double cap = 1.0;
+  const double hc = std::max(std::max(16.0 * g.r_deg, 2.0001 * g.rpad_deg), cap / 4096.0);
+  int64_t nzs = 0, nzn = 0;
+  double mid_lo = f.dec_lo, mid_hi = f.dec_hi;
+  if (hc < h && f.dec_lo < -90.0 + cap) {
+    nzs = (int64_t)std::ceil((std::min(-90.0 + cap, f.dec_hi) - f.dec_lo) / hc);
+    mid_lo = f.dec_lo + (double)nzs * hc;
+  }
+  if (hc < h && f.dec_hi > 90.0 - cap) {
+    mid_hi = std::max(90.0 - cap, mid_lo);
+    nzn = (int64_t)std::ceil((f.dec_hi - mid_hi) / hc);
+  }
+  const int64_t nzm = (nzs || nzn) ? std::max<int64_t>(1, (int64_t)std::floor((mid_hi - mid_lo) / h)) : 0;
+  // (at most 65536 zones in all, as without the bands)
+  if ((nzs || nzn) && mid_hi - mid_lo >= h && nzs + nzm + nzn <= 65536) {
+    h = (mid_hi - mid_lo) / (double)nzm;
+    nz = nzs + nzm + nzn;
+    g.dec_s = mid_lo;
+    g.dec_n = mid_hi;
+    g.nzs = (int32_t)nzs;
+    g.nzn = (int32_t)nzn;
+  }
+  g.hc_deg = g.nzs || g.nzn ? hc : h;
+  g.inv_hc = 1.0 / g.hc_deg;
   g.h_deg = h;
   g.inv_h = 1.0 / h;
   g.nz = (int32_t)nz;
-  g.dec0 = f.dec_lo;
   // at least one zone bit: the shift by rb + fb that extracts the zone must
   // stay below 32
   const int zb = zone_bits(nz);
@@ -1171,7 +1202,8 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
   if (!A || !B) return HLC_E_INVAL;
   HLC_CHECK(check_opts(opts));
   if (!(r_arcsec > 0.0) || !(r_arcsec <= B->r_build)) return HLC_E_INVAL;
-  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb || A->g.fb != B->g.fb)
+  if (A->g.h_deg != B->g.h_deg || A->g.rb != B->g.rb || A->g.fb != B->g.fb || A->g.nzs != B->g.nzs ||
+      A->g.nzn != B->g.nzn || A->g.hc_deg != B->g.hc_deg || A->g.dec_s != B->g.dec_s)
     return HLC_E_INVAL;
   if (opts->capacity > 0 && (!out_pairs || (!(opts->flags & HLC_NO_SEP) && !out_sep_arcsec)))
     return HLC_E_INVAL;

@@ -29,10 +29,15 @@ constexpr int MAXR = 4;                               // B ranges kept per group
 // bin) only; frac rides along and tightens the RA windows. Sources outside
 // the frame are clamped into its edge cells (monotone, so still correct).
 struct Geom {
-  double h_deg;       // zone height (deg)
+  double h_deg;       // zone height between the polar cap bands (deg)
   double inv_h;       // 1 / h_deg
   double bin_scale;   // 1 / ra_width
   double dec0;        // Dec of the lower edge of zone 0
+  double dec_s;       // lower edge of the first zone of height h_deg
+  double dec_n;       // lower edge of the north cap band (nzn > 0)
+  double hc_deg;      // zone height inside the cap bands
+  double inv_hc;      // 1 / hc_deg
+  int32_t nzs, nzn;   // zones of the south and north cap bands (0: none)
   double ra0;         // RA of the lower edge of bin 0
   double ra_width;    // bin width (deg)
   double r_deg;       // r_arcsec / 3600
@@ -115,11 +120,38 @@ __host__ __device__ inline bool valid_pos(double ra, double dec) {
   return (ra >= 0.0) && (ra <= 360.0) && (dec >= -90.0) && (dec <= 90.0);
 }
 
+// Zones: nzs of height hc_deg from dec0 (south cap band), then zones of
+// height h_deg from dec_s, then nzn of height hc_deg from dec_n (north cap
+// band). Each band clamps to its own zones, so the map is monotone in dec.
 __host__ __device__ inline int32_t zone_of(const Geom& g, double dec) {
-  double t = floor((dec - g.dec0) * g.inv_h);
-  if (!(t >= 0.0)) return 0;
-  if (t > (double)(g.nz - 1)) return g.nz - 1;
-  return (int32_t)t;
+  double t;
+  int32_t base, top;
+  if (g.nzs > 0 && dec < g.dec_s) {
+    t = floor((dec - g.dec0) * g.inv_hc);
+    base = 0;
+    top = g.nzs - 1;
+  } else if (g.nzn > 0 && dec >= g.dec_n) {
+    t = floor((dec - g.dec_n) * g.inv_hc);
+    base = g.nz - g.nzn;
+    top = g.nz - 1;
+  } else {
+    t = floor((dec - g.dec_s) * g.inv_h);
+    base = g.nzs;
+    top = g.nz - g.nzn - 1;
+  }
+  if (!(t >= 0.0)) return base;
+  if (t > (double)(top - base)) return top;
+  return base + (int32_t)t;
+}
+
+// lower edge and height of zone z
+__host__ __device__ inline double zone_lo(const Geom& g, int32_t z) {
+  if (z < g.nzs) return g.dec0 + (double)z * g.hc_deg;
+  if (z >= g.nz - g.nzn) return g.dec_n + (double)(z - (g.nz - g.nzn)) * g.hc_deg;
+  return g.dec_s + (double)(z - g.nzs) * g.h_deg;
+}
+__host__ __device__ inline double zone_height(const Geom& g, int32_t z) {
+  return (z < g.nzs || z >= g.nz - g.nzn) ? g.hc_deg : g.h_deg;
 }
 
 __host__ __device__ inline uint32_t bin_of(const Geom& g, double ra) {

@@ -344,8 +344,8 @@ __global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double* __res
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (uint32_t)g.nz) {
     const int32_t z = (int32_t)i;
-    double lo = g.dec0 + (double)z * g.h_deg;
-    double hi = lo + g.h_deg;
+    double lo = zone_lo(g, z);
+    double hi = lo + zone_height(g, z);
     // largest |Dec| a source assigned to this zone can have (padded for the
     // rounding of the zone formula)
     double dstar = fmin(fmax(fabs(lo), fabs(hi)) + 1e-9, 90.0);

@@ -702,8 +702,9 @@ void fill_stats(const Counters& h, int64_t na, int64_t nb, int64_t nbh, const Ge
   g_stats.zone_height_arcsec = g.h_deg * 3600.0;
 }
 
-// Stage times from the event slots: 0 start; 14 frame known; 5 A's keygen
-// done and 1 B's keygen done (call's stream, in that order); B's sort and
+// Stage times from the event slots: 0 start; 14 counters cleared; 5 A's
+// keygen done (side stream) and 1 B's keygen done (call's stream, the two
+// side by side); B's sort and
 // layout 2-4 on the call's stream; A's sort 6 (and 7) on the side stream;
 // 12 both sorts done, 8 ranges done (side stream, beside B's layout); 13
 // filter start; 9 filter; 10 certification and packing; 11 end. Stages on
@@ -711,7 +712,7 @@ void fill_stats(const Counters& h, int64_t na, int64_t nb, int64_t nbh, const Ge
 void fill_times(Device& dev, bool with_partition) {
   auto el = [&](int a, int b) { return (double)elapsed(dev.ev[a], dev.ev[b]); };
   if (with_partition) {
-    g_stats.t_keygen_ms = el(14, 5) + el(5, 1);
+    g_stats.t_keygen_ms = std::max(el(14, 5), el(14, 1));
     g_stats.t_sort_ms = el(2, 3) + el(5, 6);
     g_stats.t_layout_ms = el(3, 4) + el(6, 7);
     g_stats.t_ranges_ms = el(12, 8);
@@ -781,7 +782,11 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
       lay(c);
       if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
       launch_zero_counters(dev->cnt, s);
-      partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, s);
+      // on the side stream, where A's sort follows: B's keygen can then run
+      // beside it as soon as the host knows the frame
+      HLC_TRY(hipEventRecord(dev->fork, s));
+      HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
+      partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
       spec = true;
     }
   }
@@ -798,23 +803,27 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   lay(c);
 
   if (!keep_a) {
+    if (spec) {
+      // the speculative keys are dropped: their kernel ends before the
+      // counters are cleared again
+      HLC_TRY(hipEventRecord(dev->prepped, dev->side));
+      HLC_TRY(hipStreamWaitEvent(s, dev->prepped, 0));
+    }
     if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
     launch_zero_counters(dev->cnt, s);
   }
-  // A's partition on the side stream, B's on the caller's; the ranges run on
-  // the side stream once both are sorted, beside B's gather (separate sort
-  // scratch, disjoint counter fields)
+  // A's partition on the side stream, B's on the caller's, the two keygens
+  // side by side; the ranges run on the side stream once both are sorted,
+  // beside B's gather (separate sort scratch, disjoint counter fields)
   if (!self) {
-    // A's keys on the caller's stream ahead of B's, so that the hand-over to
-    // the side stream waits under B's keygen
-    if (!keep_a) partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, s);
-    HLC_TRY(hipEventRecord(dev->fork, s));
-    HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
+    if (!keep_a) {
+      HLC_TRY(hipEventRecord(dev->fork, s));
+      HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
+      partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
+    }
   } else {
     mark(*dev, slA.keygen, s);
   }
-  // B's keygen queued before A's sort launches, so that it follows A's keygen
-  // on the device without waiting for the host to launch A's radix passes
   partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
   if (!self) HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
   HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, sc, B, slB, s, dev->bsorted));

@@ -602,11 +602,16 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   // the candidate regions are cleared before the join, beside the ranges
   const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
   launch_regions_reset(oa, s);
+  // The filter and what follows run on ps after the ranges, once B's records
+  // are gathered on s (that event is usually complete by then, so the join
+  // costs no latency); the caller reads the counters on ps.
+  hipStream_t ts = s;
   if (ps != s) {
-    (void)hipEventRecord(dev.prepped, ps);
-    (void)hipStreamWaitEvent(s, dev.prepped, 0);
+    (void)hipEventRecord(dev.prepped, s);
+    (void)hipStreamWaitEvent(ps, dev.prepped, 0);
+    ts = ps;
   }
-  if (prof) (void)hipEventRecord(dev.ev[13], s);
+  if (prof) (void)hipEventRecord(dev.ev[13], ts);
   MatchArgs ma{};
   ma.ranges = w.ranges;
   ma.na = A.cnt;
@@ -635,12 +640,12 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.b_err = rad.b_err;
   ma.k_sigma = rad.k;
   ma.hp_order = -1;
-  launch_filter(ma, oa, fp32, filter_items, s);
-  if (prof) (void)hipEventRecord(dev.ev[9], s);
-  launch_cand(ma, oa, fp32, s);
-  launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, s);
-  launch_compact(oa, s);
-  if (prof) (void)hipEventRecord(dev.ev[10], s);
+  launch_filter(ma, oa, fp32, filter_items, ts);
+  if (prof) (void)hipEventRecord(dev.ev[9], ts);
+  launch_cand(ma, oa, fp32, ts);
+  launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, ts);
+  launch_compact(oa, ts);
+  if (prof) (void)hipEventRecord(dev.ev[10], ts);
 }
 
 size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, const Caps& caps,
@@ -836,7 +841,8 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   mark(*dev, prof ? 12 : -1, dev->side);
   match(*dev, A, B, g, r_arcsec, fp32, self, self, rad, w, out_pairs,
         (o->flags & HLC_NO_SEP) ? nullptr : out_sep, (uint64_t)o->capacity, prof, tuned_items(o), s, dev->side);
-  HLC_CHECK(read_counters(*dev, s, prof));
+  // the match ended on the side stream (after every kernel of the call on s)
+  HLC_CHECK(read_counters(*dev, dev->side, prof));
 
   const Counters& h = *dev->cnt_host;
   if (h.err) {

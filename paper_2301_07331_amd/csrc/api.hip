@@ -773,11 +773,11 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
     carve_sort(c, sc, 2 * nB);
     carve_match_ws(c, w, nA, g, caps, true);
   };
-  // While the host waits for the sample, A's keys under the whole-sphere
-  // frame are computed if the previous call on this device had that frame
-  // and the workspace already fits it (the places of A's buffers do not
-  // depend on the frame). They are kept if the sample confirms the frame,
-  // else computed again.
+  // While the host waits for the sample, A's and B's keys under the
+  // whole-sphere frame are computed if the previous call on this device had
+  // that frame and the workspace already fits it (the places of their
+  // buffers do not depend on the frame). They are kept if the sample
+  // confirms the frame, else computed again.
   bool spec = false;
   if (!self && dev->last_full) {
     Carve sizing{nullptr};
@@ -787,18 +787,20 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
       lay(c);
       if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
       launch_zero_counters(dev->cnt, s);
-      // on the side stream, where A's sort follows: B's keygen can then run
-      // beside it as soon as the host knows the frame
+      // A's on the side stream, where A's sort follows, B's beside it on the
+      // caller's stream (the places of B's buffers do not depend on the frame
+      // either)
       HLC_TRY(hipEventRecord(dev->fork, s));
       HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
       partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
+      partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
       spec = true;
     }
   }
   Frame f;
   HLC_CHECK(frame_finish(*dev, seq, a_ra, a_dec, na_frame, b_ra, b_dec, nb, s, &f));
   dev->last_full = is_full(f);
-  const bool keep_a = spec && dev->last_full;
+  const bool keep = spec && dev->last_full;  // the speculative keys stand
   g = make_geom(r_arcsec, tuned_height(o), na, nb, tuned_bins(o), f);
   g.frac_sorted = tuned_fraction_sort(o) ? 1 : 0;
   Carve sizing{nullptr};
@@ -807,7 +809,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   Carve c{(char*)dev->ws};
   lay(c);
 
-  if (!keep_a) {
+  if (!keep) {
     if (spec) {
       // the speculative keys are dropped: their kernel ends before the
       // counters are cleared again
@@ -821,7 +823,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   // side by side; the ranges run on the side stream once both are sorted,
   // beside B's gather (separate sort scratch, disjoint counter fields)
   if (!self) {
-    if (!keep_a) {
+    if (!keep) {
       HLC_TRY(hipEventRecord(dev->fork, s));
       HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
       partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
@@ -829,7 +831,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   } else {
     mark(*dev, slA.keygen, s);
   }
-  partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
+  if (!keep) partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
   if (!self) HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
   HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, sc, B, slB, s, dev->bsorted));
   if (self) {

@@ -553,3 +553,33 @@ def test_fraction_sort(hlc, prec):
     keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 1.0, prec, tuning=fs)
     assert_same(keys, sep, ref, label="fraction_sort stress 2M")
     _print("fraction_sort stress 2M", hlc.last_stats())
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_polar_band_edges(hlc, prec):
+    """Whole-sphere frame with the polar cap bands: dense sources around
+    |Dec| = 89 deg (where the zone height changes) and around the poles, with
+    counterparts on rings of about r, so that pairs cross the band edges and
+    the thin cap zones; a uniform background keeps the frame whole."""
+    g = synth.rng(909, 0)
+    ARC = 1.0 / 3600.0
+    bg_a = synth.uniform_sphere(g, 20000)
+    bg_b = synth.uniform_sphere(g, 20000)
+    for r in (0.5, 2.0, 7.0):
+        parts_a, parts_b = [bg_a], [bg_b]
+        for d0 in (89.0, -89.0, 89.9999, -89.9999):
+            n = 6000
+            ra = g.uniform(0.0, 360.0, n)
+            dec = np.clip(d0 + g.uniform(-30.0, 30.0, n) * r * ARC, -90.0, 90.0)
+            parts_a.append((ra, dec))
+            parts_b.append(synth.ring_offset(g, ra[: n // 2], dec[: n // 2], 0.9 * r * ARC, 1.1 * r * ARC))
+        a_ra = synth._wrap_ra(np.concatenate([p[0] for p in parts_a]))
+        a_dec = np.concatenate([p[1] for p in parts_a])
+        b_ra = synth._wrap_ra(np.concatenate([p[0] for p in parts_b]))
+        b_dec = np.clip(np.concatenate([p[1] for p in parts_b]), -90.0, 90.0)
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        assert len(ref) > 1000, r
+        for tun in (None, {"fraction_sort": 1}):
+            keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec, tuning=tun)
+            assert_same(keys, sep, ref, label=f"polar band edges r={r} tuning={tun}")
+        _print("polar band edges r", r, "pairs", len(ref), hlc.last_stats())

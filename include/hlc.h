@@ -79,7 +79,9 @@ typedef struct {
 
 /* Optional fixed tuning; zero fields mean "choose automatically". */
 typedef struct hlc_tuning {
-  double zone_height_arcsec; /* Dec zone height; >= 2.0001 r is enforced       */
+  double zone_height_arcsec; /* Dec zone height (within 1 deg of a pole the    *
+                              * zones are min(this, ~16 r) high); >= 2.0001 r *
+                              * is enforced                                    */
   int32_t ra_bins_log2;      /* log2 of RA bins per zone, 1..30 (0 = auto)     */
   int32_t filter_items;       /* work items (four groups of 16 A) per wave of   *
                               * the filter kernel (0 = one)                    */

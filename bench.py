@@ -5,10 +5,12 @@ filter, certification, output packing, count read-back) on FP64 inputs
 already resident in HBM. The headline value uses the FP32+recheck filter;
 the plain FP64 filter is timed beside it. Also measured (the "forms" field):
 the batched form on 10,000 cone jobs against one plain FP64 call per job,
-and the emulated HEALPix + quad-direction partition (completeness loss
-against the exact pair set, and time). Prints one JSON line.
+the emulated HEALPix + quad-direction partition (completeness loss against
+the exact pair set, and time), the streaming form on 400M x 100M held in
+pinned host memory (PCIe-inclusive) and the 20M x 20M precision stress at
+r = 0.5, 1 and 5 arcsec. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms xmatch,batch,quad]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms xmatch,batch,quad,stream,stress]
 """
 from __future__ import annotations
 
@@ -94,6 +96,101 @@ def traffic_from_pmc(fetch_dir, write_dir, kernel="k_filter<true>"):
             "source_sha256": kernel_sources_sha256()}
 
 
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def short_kernel(name):
+    """'void hlc::(anonymous namespace)::k_filter<true>(hlc::MatchArgs, ...)' -> 'k_filter<true>'."""
+    import re
+    head = name.split("(hlc::")[0].split("(unsigned")[0].split("(double")[0].split("(float")[0]
+    head = re.sub(r"^void ", "", head)
+    head = head.split("::")[-1] if "<" not in head else re.sub(r"^.*::(?=[^:<]*<)", "", head)
+    return head.strip()
+
+
+def pmc_summary(ktrace_dir, pmc_dirs):
+    """Per-kernel table from one rocprofv3 --kernel-trace --stats run and
+    several --pmc runs of the same command with --copy-calibration: average
+    duration, HBM bytes fetched and written per dispatch (FETCH_SIZE and
+    WRITE_SIZE in KiB, each scaled by what it reads for the 1 GiB device
+    copy), achieved GB/s of that traffic, and per-wave instruction counts,
+    wait and LDS-conflict figures where the passes hold them. Markdown."""
+    import csv
+    from collections import defaultdict
+    dur = {}
+    for f in _csvs(ktrace_dir, "kernel_stats.csv"):
+        for r in csv.DictReader(open(f)):
+            dur[short_kernel(r["Name"])] = float(r["AverageNs"]) * 1e-3
+    vals = defaultdict(lambda: defaultdict(list))  # kernel -> counter -> per-dispatch values
+    copy = defaultdict(list)
+    for d in pmc_dirs:
+        for f in _csvs(d, "counter_collection.csv"):
+            for r in csv.DictReader(open(f)):
+                k = r["Kernel_Name"]
+                v = float(r["Counter_Value"])
+                c = r["Counter_Name"]
+                if "hlc" not in k and ("copy" in k.lower() or "elementwise" in k.lower()):
+                    copy[c].append(v)
+                elif "hlc" in k:
+                    vals[short_kernel(k)][c].append(v)
+    gib_kib = float(1 << 20)
+    scale = {c: gib_kib / max(copy[c]) for c in ("FETCH_SIZE", "WRITE_SIZE") if copy.get(c)}
+    mean = lambda x: sum(x) / len(x) if x else None
+    rows = []
+    for k in sorted(vals, key=lambda k: -(dur.get(k) or 0)):
+        c = vals[k]
+        f = mean(c.get("FETCH_SIZE", []))
+        w = mean(c.get("WRITE_SIZE", []))
+        fb = f * scale["FETCH_SIZE"] * 1024 if f is not None and "FETCH_SIZE" in scale else None
+        wb = w * scale["WRITE_SIZE"] * 1024 if w is not None and "WRITE_SIZE" in scale else None
+        t = dur.get(k)
+        waves = mean(c.get("SQ_WAVES", []))
+        per_wave = lambda n: (mean(c[n]) / waves) if waves and c.get(n) else None
+        wait = (mean(c["SQ_WAIT_ANY"]) / mean(c["SQ_WAVE_CYCLES"])
+                if c.get("SQ_WAIT_ANY") and c.get("SQ_WAVE_CYCLES") and mean(c["SQ_WAVE_CYCLES"]) else None)
+        gbs = ((fb or 0) + (wb or 0)) / (t * 1e-6) / 1e9 if t and (fb is not None or wb is not None) else None
+        rows.append((k, t, fb, wb, gbs, waves, per_wave("SQ_INSTS_VALU"), per_wave("SQ_INSTS_VMEM_RD"),
+                     per_wave("SQ_INSTS_VMEM_WR"), per_wave("SQ_INSTS_LDS"), mean(c.get("SQ_LDS_BANK_CONFLICT", [])),
+                     wait))
+    fmt = lambda x, p="{:.3g}": "-" if x is None else p.format(x)
+    out = ["| kernel | avg us | fetched B | written B | GB/s (fetch+write) | frac of 8 TB/s | waves | VALU/wave "
+           "| VMEM rd/wave | VMEM wr/wave | LDS/wave | LDS bank-conflict cycles | wait/wave-cycles |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (k, t, fb, wb, gbs, waves, valu, vr, vw, lds, bc, wait) in rows:
+        out.append(f"| {k} | {fmt(t, '{:.1f}')} | {fmt(fb)} | {fmt(wb)} | {fmt(gbs, '{:.0f}')} | "
+                   f"{fmt(gbs / HBM_PEAK_GBS if gbs else None, '{:.3f}')} | {fmt(waves, '{:.0f}')} | {fmt(valu, '{:.0f}')} | "
+                   f"{fmt(vr, '{:.1f}')} | {fmt(vw, '{:.1f}')} | {fmt(lds, '{:.1f}')} | {fmt(bc, '{:.3g}')} | "
+                   f"{fmt(wait, '{:.2f}')} |")
+    out.append("")
+    out.append(f"copy scaling: " + ", ".join(f"{c} x{v:.4f}" for c, v in scale.items()))
+    return "\n".join(out)
+
+
+def warm_up(call, calls, seconds=0.3):
+    """Untimed calls: at least `calls` of them and at least `seconds` of them,
+    so the GPU has left its idle clocks before the timed region."""
+    import torch
+    t0 = time.perf_counter()
+    k = 0
+    while k < calls or time.perf_counter() - t0 < seconds:
+        call()
+        k += 1
+    torch.cuda.synchronize()
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -106,10 +203,15 @@ def parse():
     p.add_argument("--zone-height", type=float, default=0.0, help="arcsec; 0 = automatic")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
-    p.add_argument("--forms", default="xmatch,batch,quad",
+    p.add_argument("--forms", default="xmatch,batch,quad,stream,stress",
                    help="xmatch (the headline, always run), batch (10,000 jobs), quad (paper-scheme "
                         "emulation), stream (400M x 100M from pinned host memory) and stress (20M x 20M "
-                        "precision stress at r = 0.5, 1, 5 arcsec); the last two are not in the default set")
+                        "precision stress at r = 0.5, 1, 5 arcsec)")
+    p.add_argument("--no-single-thread", action="store_true",
+                   help="skip the single-thread oracle timings of the patch and full-sky workloads")
+    p.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                   help="print a per-kernel counter table from a rocprofv3 --kernel-trace --stats folder "
+                        "followed by one or more --pmc folders, and exit")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="print the filter kernel's HBM traffic from two rocprofv3 --pmc output folders and exit")
     return p.parse_args()
@@ -144,8 +246,27 @@ def bench_batch(hlc, torch, dev, steps, warmup):
             st, n = hlc.hlc_xmatch_batch(table, a_ra, a_dec, b_ra, b_dec, out, sep, cnt, precision=prec)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
-        res[name] = {"ms_per_call": ms, "a_sources_per_s": len(b.a_ra) / (ms * 1e-3), "pairs": int(n)}
-        print(f"[bench] batch {name}: {ms:.3f} ms/call, {n} pairs", file=sys.stderr, flush=True)
+        s_ = hlc.last_stats()
+        res[name] = {"ms_per_call": ms, "a_sources_per_s": len(b.a_ra) / (ms * 1e-3), "pairs": int(n),
+                     "tuned": {"zone_height_factor": s_["zone_height_arcsec"], "batch_tile": int(s_["batch_tile"]),
+                               "batch_blocks_per_cu": int(s_["batch_blocks_per_cu"])}}
+        print(f"[bench] batch {name}: {ms:.3f} ms/call, {n} pairs, tuned {res[name]['tuned']}", file=sys.stderr,
+              flush=True)
+        # the same call at the untuned defaults (factor 1, 1024-source tiles, 4 blocks per CU)
+        dflt = {"zone_height_factor": 1.0, "batch_tile": 1024, "batch_blocks_per_cu": 4}
+        for _ in range(max(1, warmup)):
+            hlc.hlc_xmatch_batch(table, a_ra, a_dec, b_ra, b_dec, out, sep, cnt, precision=prec, tuning=dflt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, nd = hlc.hlc_xmatch_batch(table, a_ra, a_dec, b_ra, b_dec, out, sep, cnt, precision=prec,
+                                          tuning=dflt)
+        torch.cuda.synchronize()
+        msd = (time.perf_counter() - t0) / steps * 1e3
+        if st != hlc.HLC_OK or nd != n:
+            raise RuntimeError(f"batch {name} at the default configuration: status {st}, {nd} pairs vs {n}")
+        res[name]["default_ms_per_call"] = msd
+        print(f"[bench] batch {name} default configuration: {msd:.3f} ms/call", file=sys.stderr, flush=True)
     # plain FP64: one call per job
     jout = torch.empty((max(int(b.na.max()), 1024), 2), dtype=torch.int32, device=dev)
     jsep = torch.empty(jout.shape[0], dtype=torch.float64, device=dev)
@@ -289,6 +410,9 @@ def bench_quad(hlc, torch, a_ra, a_dec, b_ra, b_dec, r, out, sep, exact_pairs):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1:]))
+        return
     if args.traffic_from:
         print(json.dumps(traffic_from_pmc(*args.traffic_from)))
         return
@@ -330,26 +454,39 @@ def main():
     results = {}
     for name in args.precisions.split(","):
         prec = hlc.HLC_FP32_RECHECK if name == "fp32" else hlc.HLC_FP64
-        for _ in range(args.warmup):
-            st, n = hlc.hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r, out, sep, precision=prec, tuning=tuning)
+        def one():
+            st, _ = hlc.hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r, out, sep, precision=prec, tuning=tuning)
             if st != hlc.HLC_OK:
                 raise hlc.HLCError(st, "warmup")
-        stats = []
+        warm_up(one, args.warmup)
+        # timed steps: the filter kernel alone is timed by two HIP events on
+        # its stream (HLC_TIME_FILTER); the per-stage events of HLC_PROFILE
+        # are taken in separate calls after the timed region
+        filt = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             st, n = hlc.hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r, out, sep, precision=prec,
-                                   flags=hlc.HLC_PROFILE, tuning=tuning)
+                                   flags=hlc.HLC_TIME_FILTER, tuning=tuning)
             if st != hlc.HLC_OK:
                 raise hlc.HLCError(st, "timed step")
-            stats.append(hlc.last_stats())
+            filt.append(hlc.last_stats()["t_match_ms"])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = wall / args.steps * 1e3
+        stats = []
+        for _ in range(3):
+            st, n = hlc.hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r, out, sep, precision=prec,
+                                   flags=hlc.HLC_PROFILE, tuning=tuning)
+            if st != hlc.HLC_OK:
+                raise hlc.HLCError(st, "profiled step")
+            stats.append(hlc.last_stats())
         s0 = stats[-1]
         stage = {k: statistics.median(s[k] for s in stats)
                  for k in ("t_keygen_ms", "t_sort_ms", "t_layout_ms", "t_ranges_ms", "t_match_ms",
                            "t_certify_ms", "t_total_ms")}
+        # the filter's time in the timed steps (HIP events on its stream)
+        stage["t_match_ms"] = statistics.mean(filt)
         mb = MATCH_BYTES[name](na, s0["nb_halo"], s0["n_band"])
         results[name] = dict(ms_per_step=ms, n_pairs=int(n), stage_ms=stage, nb_halo=int(s0["nb_halo"]),
                              n_candidates=int(s0["n_candidates"]), n_band=int(s0["n_band"]),
@@ -406,9 +543,21 @@ def main():
         cpu = {"value": na / t, "unit": "A-sources/s", "cores": threads, "kind": "oracle",
                "sample": f"whole workload ({na}x{nb}, r={r}\"), median of {args.cpu_reps} runs, "
                          f"{t:.2f} s each, unsorted output",
-               "pairs": npairs}
+               "pairs": npairs, "cpu_model": cpu_model()}
         if npairs != head["n_pairs"]:
             raise RuntimeError(f"oracle found {npairs} pairs, GPU {head['n_pairs']}")
+        if not args.no_single_thread:
+            one = {}
+            patch = synth.patch_pair()
+            for label, c in (("patch_100k", patch), ("fullsky", cat)):
+                reps = 3 if c.na <= 1_000_000 else 1
+                ts = [oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, nthreads=1, sort=False).seconds
+                      for _ in range(reps)]
+                ts1 = statistics.median(ts)
+                one[label] = {"seconds": ts1, "a_sources_per_s": c.na / ts1, "na": c.na, "nb": c.nb,
+                              "runs": reps}
+                print(f"[bench] oracle single thread {label}: {ts1:.2f} s", file=sys.stderr, flush=True)
+            cpu["single_thread"] = one
 
     line = {
         "metric": "A-sources matched/s at 10Mx10M, r=2\" (FP32+recheck vs FP64); % HBM roofline",

@@ -72,6 +72,9 @@ typedef struct {
 #define HLC_PROFILE 0x2u  /* time each stage with HIP events (hlc_last_stats)  */
 #define HLC_SORTED 0x4u   /* pairs (and separations) ordered by (a, b); not   *
                            * with hlc_xmatch_stream (HLC_E_UNSUPPORTED)       */
+#define HLC_TIME_FILTER 0x10u /* time the filter kernel alone with two HIP   *
+                           * events on its stream (hlc_last_stats           *
+                           * t_match_ms); much lighter than HLC_PROFILE     */
 #define HLC_SELF 0x8u     /* self-match: B is the same arrays as A; each       *
                            * unordered pair is reported once as (i, j), i < j, *
                            * and (i, i) never (the self-match data sets of     *
@@ -91,7 +94,11 @@ typedef struct hlc_tuning {
                               * partition also sorts the RA sub-bin bits (one  *
                               * more radix pass; narrower windows inside dense *
                               * clumps); 0 = not                               */
-  int32_t reserved[3];
+  int32_t batch_tile;        /* batched form: sources per partition tile (256, *
+                              * 512, 1024 or 2048; 0 = autotuned and cached)   */
+  int32_t batch_blocks_per_cu; /* batched form: blocks of the persistent match *
+                              * per compute unit (1..8; 0 = autotuned, cached) */
+  int32_t reserved[1];
 } hlc_tuning;
 
 typedef struct hlc_opts {
@@ -103,7 +110,8 @@ typedef struct hlc_opts {
   const hlc_tuning *tuning;  /* NULL = automatic                               */
 } hlc_opts;
 
-/* Per-call statistics of the last call on this thread's library context. */
+/* Statistics of the last call made on the calling thread (each thread keeps *
+ * its own record).                                                         */
 typedef struct hlc_stats {
   int64_t na, nb;            /* catalogue sizes                               */
   int64_t nb_halo;           /* B entries after Dec-halo duplication          */
@@ -118,7 +126,10 @@ typedef struct hlc_stats {
    * the filter kernel alone; t_certify_ms the candidate certification, the
    * band list and the packing of the output */
   double t_keygen_ms, t_sort_ms, t_layout_ms, t_ranges_ms, t_match_ms, t_certify_ms, t_total_ms;
-  double reserved[8];
+  /* batched form: the partition tile and the match blocks per compute unit
+   * used (zone_height_arcsec then holds the zone-height factor used)       */
+  double batch_tile, batch_blocks_per_cu;
+  double reserved[6];
 } hlc_stats;
 
 /* Cross-match A against B at radius r_arcsec (the paper's section 3.1 kernel
@@ -182,9 +193,12 @@ int hlc_xmatch_part(const struct hlc_part *A, const struct hlc_part *B, double r
  *   out_pairs / out_sep: device, capacity opts->capacity; pair indices are
  *     GLOBAL (into the packed arrays).
  *   job_pair_count [njobs]: device int64, pairs found per job (may be NULL).
- *   opts->tuning->zone_height_factor: 0 or no tuning = autotuned on first
- *     use for this batch shape and cached (in memory, and in the JSON file
- *     named by $HLC_TUNE_CACHE when set).
+ *   opts->tuning: zone_height_factor, batch_tile and batch_blocks_per_cu;
+ *     each one that is 0 (or no tuning) is autotuned on first use for this
+ *     batch shape on this device (timed candidate runs, one knob after the
+ *     other) and cached in memory, and in the JSON file named by
+ *     $HLC_TUNE_CACHE when set (keyed by the device's gfx architecture and
+ *     compute-unit count and by the batch's size class).
  * Total pairs go to *opts->n_pairs; overflow behaves as in hlc_xmatch.     */
 typedef struct hlc_job {
   int64_t a_off, na, b_off, nb;

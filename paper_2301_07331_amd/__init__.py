@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhlc.so")
 
 HLC_OK, HLC_E_INVAL, HLC_E_NOMEM, HLC_E_OVERFLOW, HLC_E_DEVICE, HLC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 HLC_FP32_RECHECK, HLC_FP64 = 0, 1
-HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF = 0x1, 0x2, 0x4, 0x8
+HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF, HLC_TIME_FILTER = 0x1, 0x2, 0x4, 0x8, 0x10
 
 EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
            "hlc_xmatch_stream", "hlc_transfer_model", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
@@ -24,7 +24,8 @@ EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition",
 class hlc_tuning(C.Structure):
     _fields_ = [("zone_height_arcsec", C.c_double), ("ra_bins_log2", C.c_int32),
                 ("filter_items", C.c_int32), ("zone_height_factor", C.c_double),
-                ("fraction_sort", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("fraction_sort", C.c_int32), ("batch_tile", C.c_int32), ("batch_blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class hlc_opts(C.Structure):
@@ -39,7 +40,8 @@ class hlc_stats(C.Structure):
                 ("n_zones", C.c_int32), ("ra_bits", C.c_int32), ("zone_height_arcsec", C.c_double),
                 ("t_keygen_ms", C.c_double), ("t_sort_ms", C.c_double), ("t_layout_ms", C.c_double),
                 ("t_ranges_ms", C.c_double), ("t_match_ms", C.c_double), ("t_certify_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("reserved", C.c_double * 8)]
+                ("t_total_ms", C.c_double), ("batch_tile", C.c_double), ("batch_blocks_per_cu", C.c_double),
+                ("reserved", C.c_double * 6)]
 
 
 class hlc_job(C.Structure):
@@ -146,6 +148,8 @@ def make_opts(precision=HLC_FP32_RECHECK, capacity=0, stream=None, flags=0, tuni
         tu.filter_items = int(tuning.get("filter_items", 0))
         tu.zone_height_factor = float(tuning.get("zone_height_factor", 0.0))
         tu.fraction_sort = int(tuning.get("fraction_sort", 0))
+        tu.batch_tile = int(tuning.get("batch_tile", 0))
+        tu.batch_blocks_per_cu = int(tuning.get("batch_blocks_per_cu", 0))
         o.tuning = C.pointer(tu)
     return o, n, tu
 

@@ -23,8 +23,7 @@ namespace {
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-constexpr int FT = 256;              // threads of the per-tile kernels
-constexpr int TI = BATCH_TILE / FT;  // sources per thread
+constexpr int FT = 256;              // threads of the per-tile kernels (TI sources each)
 
 __device__ inline double fold180(double x) {
   // x in (-360, 360] -> (-180, 180]
@@ -56,6 +55,7 @@ __global__ void k_job_bounds_init(unsigned long long* bounds, int32_t njobs) {
   bounds[i] = (i & 1) ? 0ull : ~0ull;  // min slots start high, max slots low
 }
 
+template <int TI>
 __global__ __launch_bounds__(FT) void k_job_bounds(const BatchTile* __restrict__ tiles, uint32_t ntiles,
                                                    const BatchJob* __restrict__ jobs,
                                                    const double* __restrict__ a_ra,
@@ -250,6 +250,7 @@ __device__ inline uint32_t job_bin(const JobGeom& G, double ra) {
 
 // keys for one side; tiles never cross jobs (tile table built on the host).
 // Entry positions are job-packed; values are the caller's global indices.
+template <int TI>
 __global__ __launch_bounds__(FT) void k_batch_keygen(const BatchTile* __restrict__ tiles,
                                                      uint32_t ntiles, const JobGeom* __restrict__ geo,
                                                      const double* __restrict__ ra,
@@ -748,11 +749,20 @@ void launch_job_bounds_init(unsigned long long* bounds, int32_t njobs, hipStream
   k_job_bounds_init<<<cdiv(4 * (uint64_t)njobs, 256), 256, 0, s>>>(bounds, njobs);
 }
 
-void launch_job_bounds(const BatchTile* tiles, uint32_t ntiles, const BatchJob* jobs, const double* a_ra,
-                       const double* b_ra, const double* ra, const double* dec, bool side_b,
+void launch_job_bounds(const BatchTile* tiles, uint32_t ntiles, int tile, const BatchJob* jobs,
+                       const double* a_ra, const double* b_ra, const double* ra, const double* dec, bool side_b,
                        unsigned long long* bounds, Counters* cnt, hipStream_t s) {
   if (ntiles == 0) return;
-  k_job_bounds<<<ntiles, FT, 0, s>>>(tiles, ntiles, jobs, a_ra, b_ra, ra, dec, side_b ? 1 : 0, bounds, cnt);
+  const int sb = side_b ? 1 : 0;
+#define HLC_JOB_BOUNDS(TI) \
+  k_job_bounds<TI><<<ntiles, FT, 0, s>>>(tiles, ntiles, jobs, a_ra, b_ra, ra, dec, sb, bounds, cnt)
+  switch (tile) {
+    case 256: HLC_JOB_BOUNDS(1); break;
+    case 512: HLC_JOB_BOUNDS(2); break;
+    case 2048: HLC_JOB_BOUNDS(8); break;
+    default: HLC_JOB_BOUNDS(4); break;
+  }
+#undef HLC_JOB_BOUNDS
 }
 
 void launch_job_frames(const BatchJob* jobs, int32_t njobs, const double* a_ra, const double* b_ra,
@@ -761,12 +771,20 @@ void launch_job_frames(const BatchJob* jobs, int32_t njobs, const double* a_ra, 
   k_job_frames<<<cdiv(njobs, 256), 256, 0, s>>>(jobs, njobs, a_ra, b_ra, bounds, lb_bits, h_factor, geo);
 }
 
-void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, const JobGeom* geo, const double* ra,
+void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, int tile, const JobGeom* geo, const double* ra,
                          const double* dec, int32_t lb_bits, bool halo, uint32_t n_total, uint32_t* keys,
                          uint32_t* vals, Counters* cnt, hipStream_t s) {
   if (ntiles == 0) return;
-  k_batch_keygen<<<ntiles, FT, 0, s>>>(tiles, ntiles, geo, ra, dec, lb_bits, halo ? 1 : 0, n_total, keys,
-                                        vals, cnt);
+  const int h = halo ? 1 : 0;
+#define HLC_BATCH_KEYGEN(TI) \
+  k_batch_keygen<TI><<<ntiles, FT, 0, s>>>(tiles, ntiles, geo, ra, dec, lb_bits, h, n_total, keys, vals, cnt)
+  switch (tile) {
+    case 256: HLC_BATCH_KEYGEN(1); break;
+    case 512: HLC_BATCH_KEYGEN(2); break;
+    case 2048: HLC_BATCH_KEYGEN(8); break;
+    default: HLC_BATCH_KEYGEN(4); break;
+  }
+#undef HLC_BATCH_KEYGEN
 }
 
 void launch_batch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,

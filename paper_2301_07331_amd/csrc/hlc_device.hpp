@@ -94,15 +94,59 @@ struct Rec64 {      // FP64 working record (32 B)
   double x, y, z;
   uint32_t idx, pad;
 };
-struct Rec32 {      // FP32 working record (16 B): the FP32 unit vector (single
-  float x, y, z;    // calls) or its offset from the job's frame centre (batched form)
+struct Rec32 {      // batched form's FP32 working record (16 B): the unit
+  float x, y, z;    // vector's offset from the job's frame centre, and the index
   uint32_t idx;
 };
-struct SrcRec32 {   // per-source FP32 record with its FP64 position (32 B)
+
+// FP32 working record of the single-call filter (16 B). The unit vector u
+// (computed in FP64) is held as the corner of its FP32 lattice cell, each
+// component rounded down to FP32 (x, y, z), and its offset inside that cell
+// per axis as a fixed-point count of CELL_UNIT = 2^-34 (10 bits per axis in
+// `off`: x in bits 0-9, y in 10-19, z in 20-29), rounded down. A cell is at
+// most 2^-24 wide on an axis (|u_k| <= 1), so the count fits 10 bits and the
+// stored position lies within 2^-34 of u on each axis, below it. The filter
+// subtracts a group centre c (another lattice corner) from the corners and
+// adds the scaled offsets, so it works in FP32 on small offsets from c
+// instead of on unit vectors of magnitude 1.
+struct CellRec32 {
   float x, y, z;
-  uint32_t idx;
+  uint32_t off;
+};
+constexpr float CELL_UNIT = 0x1p-34f;
+constexpr double CELL_SCALE = 0x1p34;
+
+// per-source FP32 record of a catalogue that the filter reads in place (32 B):
+// the cell record and the FP64 position, which share one cache line, so the
+// candidates of that catalogue carry their (ra, dec) at no extra read
+struct SrcRec32 {
+  CellRec32 c;
   double ra, dec;
 };
+
+// the cell record of a unit vector (FP64 components in [-1, 1])
+__device__ inline CellRec32 encode_cell(double x, double y, double z) {
+  CellRec32 r;
+  r.x = __double2float_rd(x);
+  r.y = __double2float_rd(y);
+  r.z = __double2float_rd(z);
+  // u - corner is exact in FP64 (below one FP32 ulp of u) and non-negative
+  auto q = [](double u, float c) {
+    const double t = floor((u - (double)c) * CELL_SCALE);
+    return (uint32_t)(t < 1023.0 ? (t > 0.0 ? t : 0.0) : 1023.0);
+  };
+  r.off = q(x, r.x) | (q(y, r.y) << 10) | (q(z, r.z) << 20);
+  return r;
+}
+
+// offset of a cell record from the centre (cx, cy, cz), in FP32:
+// fl(fl(corner - c) + count * 2^-34) per axis
+__device__ inline void cell_offset(const CellRec32& r, float cx, float cy, float cz, float& ox, float& oy,
+                                   float& oz) {
+  ox = fmaf((float)(r.off & 1023u), CELL_UNIT, r.x - cx);
+  oy = fmaf((float)((r.off >> 10) & 1023u), CELL_UNIT, r.y - cy);
+  oz = fmaf((float)(r.off >> 20), CELL_UNIT, r.z - cz);
+}
 
 // Logical block of a dispatched block such that consecutive logical blocks
 // run on the same XCD (blocks are dispatched round-robin over the 8 XCDs, each

@@ -20,14 +20,27 @@ struct SortScratch {
 
 // keys/vals for A (one entry per source, or one per source plus Dec-halo
 // copies appended after n when `halo` is set).
-// keys (and halo copies) of n sources; with src64 / src32 also each
-// source's working record in input order, for launch_gather64 / 32
+// keys (and halo copies) of n sources; with src64 (FP64 form), cell32 and
+// radec32 (FP32 form, a catalogue whose records are gathered) or src32 (FP32
+// form, a catalogue the filter reads in place) also each source's working
+// record in input order, for launch_gather64 / 32, the filter and the
+// certification
+// The first radix pass's per-tile digit counts, filled by the keygen for
+// the tiles it alone writes (the sort's scratch counts of an entry capacity
+// cap, digit shift of the first pass).
+struct KeygenHist {
+  uint32_t* counts;
+  uint32_t cap;
+  int shift;
+};
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
-                   Rec64* src64 = nullptr, SrcRec32* src32 = nullptr);
+                   Rec64* src64 = nullptr, CellRec32* cell32 = nullptr, double2* radec32 = nullptr,
+                   SrcRec32* src32 = nullptr, const KeygenHist* kh = nullptr);
+// tiles of the first pass whose counts a keygen of n sources fills
+uint32_t keygen_hist_tiles(uint32_t n);
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s);
-void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* src, Rec32* rec, double2* radec,
-                     hipStream_t s);
+void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* src, CellRec32* rec, hipStream_t s);
 
 size_t sort_counts_len(uint32_t n);
 size_t sort_digit_totals_len(uint32_t n);
@@ -41,8 +54,9 @@ int radix_passes(int key_bits, int lo_bit = 0);
 // vals, tmp_pairs, tmp_sep hold n entries each
 void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, uint32_t* keys, uint32_t* vals,
                 uint2* tmp_pairs, double* tmp_sep, const SortScratch& sc, hipStream_t s);
+// hist_done: tiles whose first-pass counts are already in sc.counts (keygen)
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt = false, int lo_bit = 0);
+                hipStream_t s, bool from_alt = false, int lo_bit = 0, uint32_t hist_done = 0);
 
 // footprint of the valid sources into Counters::ext (max-combined): a
 // sample of at most 2 x 4096 sources (overwrites; also written to msg[0..3]
@@ -54,10 +68,16 @@ void launch_extent(const double* ra, const double* dec, uint32_t n, Counters* cn
 void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream_t s);
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s);
+// the same read from the key index (requires rb + fb >= shift: every zone's
+// first key is then a multiple of the index step)
+void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const DevCount& n, const Geom& g,
+                              uint32_t* zstart, hipStream_t s);
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s);
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     Rec32* rec, double2* radec, hipStream_t s);
+                     CellRec32* rec, hipStream_t s);
+// radec[i] = (ra[i], dec[i]), i < n
+void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s);
 // lb[i] = number of B keys below keysA[i]; splits: merge_splits_len words of scratch
 size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap);
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
@@ -78,14 +98,17 @@ void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* ki
 constexpr int NREG = 256;
 constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
 
-// A staged filter candidate: everything the certification needs of the A
-// entry travels with it, so the certification reads nothing of A.
-//   (u0, u1, u2): A's FP64 unit vector (FP64 form) or (ra, dec, 0) (FP32 form)
-//   ia: A's original index (paper-scheme emulation: A's sorted position)
-//   bp: B's sorted position
+// A staged filter candidate.
+//   FP64 form: everything the certification needs of the A entry travels
+//     with it, so the certification reads nothing of A: (u0, u1, u2) is A's
+//     FP64 unit vector, ia A's original index (paper-scheme emulation: A's
+//     sorted position), b B's sorted position.
+//   FP32 form: (u0, u1) is A's (ra, dec) when the filter read it with A's
+//     record (A read in place), else NaN; ia and b are A's and B's original
+//     indices; the certification reads B's (ra, dec) by index.
 struct Cand {
   double u0, u1, u2;
-  uint32_t ia, bp;
+  uint32_t ia, b;
 };
 
 struct Regions {
@@ -156,17 +179,26 @@ struct MatchArgs {
   const Rec64* recA64;
   const Rec64* recB64;
   double t_lo64, t_hi64;        // chord^2: certain in / candidate
-  // FP32 form: FP32 unit vectors and the FP64 (ra, dec) of every entry
-  const Rec32* recA32;
-  const Rec32* recB32;
+  // FP32 form: sorted cell records, and the FP64 (ra, dec) of each source by
+  // original index (certification; srcradA may be null when A is read in
+  // place, its candidates then carry A's (ra, dec))
+  const CellRec32* recA32;
+  const CellRec32* recB32;
+  const double2* srcradA;
+  const double2* srcradB;
+  float c_r32;                  // chord of r, rounded up to FP32
+  // paper-scheme emulation: the FP64 (ra, dec) of every sorted entry
   const double2* radecA;
   const double2* radecB;
-  float thr32;                  // chord^2 bound covering the FP32 rounding
-  // A read in place (recA64 / recA32 / radecA unused): entry p's record is
-  // the keygen's per-source record of source valsA[p]
+  // sorted index arrays (source index, halo bit included)
   const uint32_t* valsA;
+  const uint32_t* valsB;
+  // A read in place (recA64 / recA32 unused): entry p's record is the
+  // keygen's per-source record of source valsA[p]
+  int a_in_place;
   const Rec64* srcA64;
   const SrcRec32* srcA32;
+  const CellRec32* cellA;       // (experiment) A's cell records in place, apart from (ra, dec)
   const uint32_t* keysA;
   const uint32_t* keysB;
   Geom geom;
@@ -233,8 +265,11 @@ struct BatchJob {          // one job as given by the caller, plus host-derived 
   uint32_t a_entry, b_entry;  // first packed entry of the job in the A / B key arrays
   uint32_t zoff, zcap;     // the job's slice of the per-(job, zone) tables; zone budget
 };
-constexpr int BATCH_TILE = 1024;  // sources per tile: 256 threads, four each
-struct BatchTile {         // <= BATCH_TILE consecutive sources of one job and one side
+constexpr int BATCH_TILE = 1024;  // default sources per tile: 256 threads, four each
+// tile sizes the batched kernels are built for (256 threads, 1, 2, 4 or 8
+// sources each)
+inline bool batch_tile_ok(int t) { return t == 256 || t == 512 || t == 1024 || t == 2048; }
+struct BatchTile {         // <= tile consecutive sources of one job and one side
   uint32_t job, entry, src, count;
 };
 struct JobGeom {           // the job's local frame (computed on the device)
@@ -264,13 +299,13 @@ struct BatchMatchArgs {
 };
 
 void launch_job_bounds_init(unsigned long long* bounds, int32_t njobs, hipStream_t s);
-void launch_job_bounds(const BatchTile* tiles, uint32_t ntiles, const BatchJob* jobs, const double* a_ra,
-                       const double* b_ra, const double* ra, const double* dec, bool side_b,
+void launch_job_bounds(const BatchTile* tiles, uint32_t ntiles, int tile, const BatchJob* jobs,
+                       const double* a_ra, const double* b_ra, const double* ra, const double* dec, bool side_b,
                        unsigned long long* bounds, Counters* cnt, hipStream_t s);
 void launch_job_frames(const BatchJob* jobs, int32_t njobs, const double* a_ra, const double* b_ra,
                        const unsigned long long* bounds, int32_t lb_bits, double h_factor, JobGeom* geo,
                        hipStream_t s);
-void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, const JobGeom* geo, const double* ra,
+void launch_batch_keygen(const BatchTile* tiles, uint32_t ntiles, int tile, const JobGeom* geo, const double* ra,
                          const double* dec, int32_t lb_bits, bool halo, uint32_t n_total, uint32_t* keys,
                          uint32_t* vals, Counters* cnt, hipStream_t s);
 void launch_batch_layout32(const uint32_t* keys, const uint32_t* vals, const DevCount& n, const double* ra,

@@ -22,8 +22,14 @@
 //   FP64: chord^2 = |u_a - u_b|^2 of FP64 unit vectors. Candidates are pairs
 //     with chord^2 <= t_hi64; below t_lo64 the pair is certainly in and its
 //     separation is 2 asin(chord/2). Between the two it goes to the band list.
-//   FP32: the same test on FP32 unit vectors against a widened bound that
-//     covers their rounding; every candidate is then certified with the FP64
+//   FP32: the same test in FP32 on offsets from a centre c of each group (the
+//     FP32 lattice corner of its middle A entry's unit vector): every record
+//     holds its unit vector as an FP32 lattice corner plus a fixed-point
+//     offset inside that cell (CellRec32); a lane forms a' = (corner - c) +
+//     offset for its A entry once per item, the lane that loads a B record
+//     forms b' the same way once per chunk, and the tests subtract and square
+//     these small offsets. The bound each lane tests against covers the
+//     rounding (below); every candidate is then certified with the FP64
 //     haversine of its (ra, dec), and only those within the FP64 band of r go
 //     to the band list.
 //
@@ -33,15 +39,26 @@
 // |chord_fp64 - chord| <= sqrt(3)*8u + u*chord ~= 1.6e-15. ETA64 = 4e-15 is
 // used for the thresholds (2.5x margin for the device libm).
 //
-// FP32 filter budget (v = 2^-24): a component rounded to FP32 errs by
-// w <= v + 5u from the exact one; the FP32 difference of two components errs
-// by <= 2w + v|d|, so the FP32 chord is <= (chord + 2 sqrt(3) w)(1 + v), and
-// the two fmas and the product add (1 + v)^3 to its square. The bound
-// (c_r (1 + 8u) + 3.5 (v + 5u))^2 (1 + 6v), rounded up to FP32, therefore
-// never rejects a true pair; at r = 2 arcsec it admits chords up to about
-// 2.04 arcsec.
+// FP32 filter budget (v = 2^-24 the FP32 unit roundoff, w = 2^-34 the cell
+// unit). A record's stored position p lies below the FP64 unit vector by
+// less than w on every axis, so two entries' stored positions differ from
+// their true difference by less than sqrt(3) w. Forming a' = fl(fl(corner -
+// c) + count w) costs at most v(|corner - c| + |a'|) per axis, the
+// difference of two offsets v|a' - b'| per axis, and the three products and
+// sums of its square (1 + v)^3. For a true pair (chord <= c_r) the B entry
+// lies within |a'| + c_r + sqrt(3) w of c, which bounds its own terms, so
+//   |a' - b'| <= c_r + E,  E = sqrt(3) w + v (4 |a'| + 2 c_r + 7 w) + 2e-15
+// (the last term: the FP64 unit vectors' own error),
+// and the computed chord^2 is at most (c_r + E)^2 (1 + v)^5. Each lane tests
+// against (c_r32 + E')^2 (1 + 2^-18) with c_r32 >= c_r and E' >= E evaluated
+// from the norm of its own a' (with margins for the FP32 evaluation of the
+// bound itself), so no true pair is rejected. With c at the middle entry of
+// a group, |a'| is at most the group's half extent: at 10M x 10M sources and
+// r = 2 arcsec the bound admits chords about 1e-4 r beyond r, where an FP32
+// filter on unit vectors needs about 0.04 arcsec.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "hlc_kernels.hpp"
@@ -105,7 +122,7 @@ struct Verdict {
 template <bool HP>
 __device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
   Verdict v{false, false, 0u, 0u, 0.0};
-  const Rec64 B = a.recB64[c.bp];
+  const Rec64 B = a.recB64[c.b];
   const double dx = c.u0 - B.x, dy = c.u1 - B.y, dz = c.u2 - B.z;
   const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
   v.ia = HP ? (a.recA64[c.ia].idx & IDX_MASK) : c.ia;
@@ -114,7 +131,7 @@ __device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
   if constexpr (HP) {
     // paper-scheme emulation: count the pair in the smallest shared pixel
     uint32_t pa[5], pb[5];
-    const double2 ca = a.radecA[c.ia], cb = a.radecB[c.bp];
+    const double2 ca = a.radecA[c.ia], cb = a.radecB[c.b];
     const int na_ = hp_quad(a.hp_order, ca.x, ca.y, a.hp_R, pa);
     const int nb_ = hp_quad(a.hp_order, cb.x, cb.y, a.hp_R, pb);
     uint32_t first = 0xffffffffu;
@@ -133,10 +150,12 @@ __device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
 
 __device__ inline Verdict certify32(const MatchArgs& a, const Cand& c) {
   Verdict v{false, false, 0u, 0u, 0.0};
-  const double2 pb = a.radecB[c.bp];
-  v.ia = c.ia;
-  v.ib = a.recB32[c.bp].idx & IDX_MASK;
-  const double h = haversine64(c.u0, c.u1, pb.x, pb.y);
+  const uint32_t ia = c.ia, ib = c.b;
+  const double2 pb = a.srcradB[ib];
+  const double2 pa = (c.u0 == c.u0) ? make_double2(c.u0, c.u1) : a.srcradA[ia];
+  v.ia = ia;
+  v.ib = ib;
+  const double h = haversine64(pa.x, pa.y, pb.x, pb.y);
   const bool keep = !a.self_only || v.ia < v.ib;
   double Hlo = a.H_lo, Hhi = a.H_hi;
   if (a.a_err) pair_hav_thr(pair_radius(a, v.ia, v.ib), Hlo, Hhi);
@@ -189,9 +208,12 @@ __global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
           const uint32_t mid = (lo + hi) >> 1;
           if (s_pre[mid] <= i) lo = mid; else hi = mid;
         }
-        const Cand c = o.reg.cand[(unsigned long long)lo * o.reg.Sc + (i - s_pre[lo])];
-        if constexpr (F32) v[j] = certify32(a, c);
-        else v[j] = certify64<HP>(a, c);
+        const unsigned long long at = (unsigned long long)lo * o.reg.Sc + (i - s_pre[lo]);
+        if constexpr (F32) {
+          v[j] = certify32(a, o.reg.cand[at]);
+        } else {
+          v[j] = certify64<HP>(a, o.reg.cand[at]);
+        }
       }
     }
 #pragma unroll
@@ -216,6 +238,7 @@ struct ALane {
   uint32_t ia, key;
 };
 
+template <bool F32>
 __device__ inline void stage_candidates(const MatchArgs& a, const OutArgs& o, const uint2* q, uint32_t qn,
                                         const ALane* al) {
   const uint32_t k = wave_region();
@@ -233,7 +256,14 @@ __device__ inline void stage_candidates(const MatchArgs& a, const OutArgs& o, co
     base = __shfl(base, (int)leader);
     if (keep) {
       const unsigned long long slot = base + rank_in(m);
-      if (slot < o.reg.Sc) o.reg.cand[(unsigned long long)k * o.reg.Sc + slot] = Cand{A.u0, A.u1, A.u2, A.ia, ent.y};
+      const unsigned long long at = (unsigned long long)k * o.reg.Sc + slot;
+      if (slot < o.reg.Sc) {
+        // FP32 form: A's (ra, dec) (NaN: not at hand) and the two original
+        // indices (the halo bit dropped); FP64: A's unit vector, A's index
+        // and B's position
+        if constexpr (F32) o.reg.cand[at] = Cand{A.u0, A.u1, 0.0, A.ia, a.valsB[ent.y] & IDX_MASK};
+        else o.reg.cand[at] = Cand{A.u0, A.u1, A.u2, A.ia, ent.y};
+      }
     }
   }
 }
@@ -261,16 +291,48 @@ struct Vec3 {
   V x, y, z;
 };
 
+// A B entry as loaded, before it is turned into the values the tests use:
+// the FP64 unit vector, or the FP32 cell record.
 template <bool F32>
-__device__ inline Vec3<typename std::conditional<F32, float, double>::type> load_rec(const MatchArgs& a, bool B,
-                                                                                    uint32_t p) {
+struct RawB;
+template <>
+struct RawB<false> {
+  double x, y, z;
+};
+template <>
+struct RawB<true> {
+  CellRec32 c;
+};
+
+template <bool F32>
+__device__ inline RawB<F32> load_b(const MatchArgs& a, uint32_t p) {
   if constexpr (F32) {
-    const Rec32 r = B ? a.recB32[p] : a.recA32[p];
-    return {r.x, r.y, r.z};
+    return RawB<true>{a.recB32[p]};
   } else {
-    const Rec64 r = B ? a.recB64[p] : a.recA64[p];
-    return {r.x, r.y, r.z};
+    const Rec64 r = a.recB64[p];
+    return RawB<false>{r.x, r.y, r.z};
   }
+}
+
+// The values the tests use: the FP64 unit vector, or the FP32 offset from
+// the row's centre (cx, cy, cz); `far` for a slot past the row's sequence.
+template <bool F32>
+__device__ inline Vec3<typename std::conditional<F32, float, double>::type> b_values(const RawB<F32>& r, bool ok,
+                                                                                     float cx, float cy, float cz) {
+  using V = typename std::conditional<F32, float, double>::type;
+  const V far = (V)1e30;
+  Vec3<V> B{far, far, far};
+  if constexpr (F32) {
+    float ox, oy, oz;
+    cell_offset(r.c, cx, cy, cz, ox, oy, oz);
+    if (ok) B = Vec3<V>{ox, oy, oz};
+  } else {
+    (void)cx;
+    (void)cy;
+    (void)cz;
+    if (ok) B = Vec3<V>{r.x, r.y, r.z};
+  }
+  return B;
 }
 
 // up to sixteen tests: bit N of mask <- |a - b_N|^2 <= thr, b_N the record of
@@ -332,11 +394,48 @@ __device__ inline Flat flatten(const ItemHead& h) {
   return f;
 }
 
+// What a lane reads of its A entry: the FP32 cell record or the FP64 unit
+// vector, what its staged candidates carry (u0..u2) and its key.
+struct ARaw {
+  CellRec32 ca;
+  double u0, u1, u2;
+  uint32_t key;
+};
+
+template <bool F32>
+__device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
+  ARaw r{{0.f, 0.f, 0.f, 0u}, 0.0, 0.0, 0.0, 0u};
+  if (!h.a_ok) return r;
+  r.key = a.keysA[h.a_pos];
+  const uint32_t idx = h.va;  // the entry's source index (halo bit included)
+  if constexpr (F32) {
+    if (a.a_in_place && a.cellA) {
+      r.ca = a.cellA[idx & IDX_MASK];
+      r.u0 = __builtin_nan("");
+    } else if (a.a_in_place) {
+      const SrcRec32 s = a.srcA32[idx & IDX_MASK];
+      r.ca = s.c;
+      r.u0 = s.ra;
+      r.u1 = s.dec;
+    } else {
+      r.ca = a.recA32[h.a_pos];
+      r.u0 = __builtin_nan("");  // the certification reads A's (ra, dec)
+    }
+  } else {
+    const Rec64 s = a.a_in_place ? a.srcA64[idx & IDX_MASK] : a.recA64[h.a_pos];
+    r.u0 = s.x;
+    r.u1 = s.y;
+    r.u2 = s.z;
+  }
+  return r;
+}
+
 // Persistent: wave w of W takes items w, w + W, ... (an item is four groups,
 // one per 16-lane row). The next item's ranges and A index are loaded
-// while the current one is tested.
-template <bool F32>
-__global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
+// while the current one is tested, and its A records once the first chunk
+// has been tested (A's records are read in place, one cache line each).
+template <bool F32, bool PREF>
+__global__ __launch_bounds__(MT, PREF ? 1 : 7) void k_filter(MatchArgs a, OutArgs o) {
   using V = typename std::conditional<F32, float, double>::type;
   __shared__ uint2 s_q[WAVES][QCAP];
   __shared__ ALane s_a[WAVES][64];
@@ -354,83 +453,77 @@ __global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
   const uint32_t ngroups = (na + GROUP - 1) / GROUP;
   const uint32_t nitems = (ngroups + 3u) / 4u;
   const V far = (V)1e30;
-  V thr;
-  if constexpr (F32) thr = a.thr32;
-  else thr = a.t_hi64;
 
   uint32_t item = blk * WAVES + w;
   ItemHead head = item_head(a, item, row, l16, na, ngroups);
+  ARaw ar = load_a<F32>(a, head);
   while (__builtin_amdgcn_readfirstlane(item) < nitems) {
     const ItemHead cur = head;
     const uint32_t next = item + W;
-    // stage 1 of this item: its first B chunk and its A record
+    // stage 1 of this item: its first B chunk (its A record is in flight)
     const Flat f = flatten(cur);
     uint32_t t = l16;
     uint32_t bp = t < f.total ? flat_pos(f, t) : 0u;
-    Vec3<V> B{far, far, far};
-    if (t < f.total) B = load_rec<F32>(a, true, bp);
+    RawB<F32> rb{};
+    if (t < f.total) rb = load_b<F32>(a, bp);
     bool a_ok = cur.a_ok;
-    Vec3<V> A{-far, -far, -far};
     // what a staged candidate carries of this lane's A entry
-    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
-    uint32_t ia = 0u, keyA = 0u;
-    if (a_ok) {
-      uint32_t idx;
-      keyA = a.keysA[cur.a_pos];
-      if (a.valsA) {
-        // valsA: the entry's source index (halo bit included)
-        idx = cur.va;
-        if constexpr (F32) {
-          const SrcRec32 r = a.srcA32[idx & IDX_MASK];
-          A = Vec3<V>{r.x, r.y, r.z};
-          u0 = r.ra;
-          u1 = r.dec;
-        } else {
-          const Rec64 r = a.srcA64[idx & IDX_MASK];
-          A = Vec3<V>{r.x, r.y, r.z};
-          u0 = r.x;
-          u1 = r.y;
-          u2 = r.z;
-        }
-      } else {
-        A = load_rec<F32>(a, false, cur.a_pos);
-        idx = F32 ? a.recA32[cur.a_pos].idx : a.recA64[cur.a_pos].idx;
-        if constexpr (F32) {
-          const double2 p = a.radecA[cur.a_pos];
-          u0 = p.x;
-          u1 = p.y;
-        } else {
-          u0 = A.x;
-          u1 = A.y;
-          u2 = A.z;
-        }
-      }
-      ia = a.hp_order >= 0 ? cur.a_pos : (idx & IDX_MASK);
-      if (a.skip_halo_a && (idx & HALO_BIT)) {
-        a_ok = false;
-        A = Vec3<V>{-far, -far, -far};
-      }
+    const uint32_t ia = !a_ok ? 0u : (a.hp_order >= 0 ? cur.a_pos : (cur.va & IDX_MASK));
+    if (a_ok && a.skip_halo_a && (cur.va & HALO_BIT)) a_ok = false;
+    s_a[w][lane] = ALane{ar.u0, ar.u1, ar.u2, ia, ar.key};
+    const CellRec32 ca = ar.ca;
+    const Vec3<double> a64{ar.u0, ar.u1, ar.u2};
+    // FP32: the row's centre is the lattice corner of its middle entry (its
+    // first when the group has eight entries or fewer); each lane's offset
+    // from it and the bound covering the filter's rounding (header comment)
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    Vec3<V> A{-far, -far, -far};
+    V thr;
+    if constexpr (F32) {
+      const bool mid = cur.grp * GROUP + 8u < na;
+      const float mx = row_bcast<8>(ca.x), my = row_bcast<8>(ca.y), mz = row_bcast<8>(ca.z);
+      const float fx = row_bcast<0>(ca.x), fy = row_bcast<0>(ca.y), fz = row_bcast<0>(ca.z);
+      cx = mid ? mx : fx;
+      cy = mid ? my : fy;
+      cz = mid ? mz : fz;
+      float ax, ay, az;
+      cell_offset(ca, cx, cy, cz, ax, ay, az);
+      // E' >= sqrt(3) w + v (4 |a'| + 2 c_r + 7 w) + 2e-15 (the FP64 unit
+      // vectors' own error): the factors 4.01 and 2.01 and the added 2^-30 v
+      // cover the FP32 evaluation of |a'| and of this bound
+      const float an = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
+      const float E = 0x1.bb68p-34f + 2e-15f + 0x1p-24f * (4.01f * an + 2.01f * a.c_r32 + 0x1p-30f);
+      const float cr = a.c_r32 + E;
+      thr = cr * cr * (1.0f + 0x1p-18f);
+      if (a_ok) A = Vec3<V>{ax, ay, az};
+    } else {
+      thr = a.t_hi64;
+      if (a_ok) A = Vec3<V>{a64.x, a64.y, a64.z};
     }
-    s_a[w][lane] = ALane{u0, u1, u2, ia, keyA};
     // stage 0 of the next item, in flight while this one is tested
     head = item_head(a, next, row, l16, na, ngroups);
 
-    // chunk c of the row covers items [16c, 16c + 16) of the concatenation
-    const uint32_t nch = (f.total + 15u) >> 4;
-    for (uint32_t c = 0; __ballot(c < nch); ++c) {
+    // chunk c of the row covers items [16c, 16c + 16) of the concatenation;
+    // the wave runs as many chunks as its longest row needs (scalar)
+    const uint32_t tmax = max(max((uint32_t)__builtin_amdgcn_readlane((int)f.total, 0),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)f.total, 16)),
+                              max((uint32_t)__builtin_amdgcn_readlane((int)f.total, 32),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)f.total, 48)));
+    const uint32_t nch = (tmax + 15u) >> 4;
+    for (uint32_t c = 0; c < nch; ++c) {
       // next chunk's record in flight while this one is tested
       const uint32_t tn = t + GROUP;
       const uint32_t bpn = tn < f.total ? flat_pos(f, tn) : 0u;
-      Vec3<V> Bn{far, far, far};
-      if (tn < f.total) Bn = load_rec<F32>(a, true, bpn);
+      RawB<F32> rbn{};
+      if (tn < f.total) rbn = load_b<F32>(a, bpn);
+      const Vec3<V> B = b_values<F32>(rb, t < f.total, cx, cy, cz);
 
       // records in this chunk: the largest count over the wave's four rows
-      uint32_t nrow = f.total > t - l16 ? min(f.total - (t - l16), (uint32_t)GROUP) : 0u;
-      nrow = max(nrow, (uint32_t)__shfl_xor((int)nrow, 16));
-      nrow = max(nrow, (uint32_t)__shfl_xor((int)nrow, 32));
-      const uint32_t nmax = __builtin_amdgcn_readfirstlane(nrow);
+      const uint32_t nmax = min(tmax - 16u * c, (uint32_t)GROUP);
       uint32_t mask = 0u;
       tests<0, V>(A, B, thr, nmax, mask);
+      // the next item's A records, once its index has arrived
+      if (PREF && c == 0) ar = load_a<F32>(a, head);
       // drain the hits into the queue, lowest bit first
       while (__ballot(mask != 0u)) {
         const bool has = mask != 0u;
@@ -441,17 +534,18 @@ __global__ __launch_bounds__(MT) void k_filter(MatchArgs a, OutArgs o) {
         qn += (uint32_t)__popcll(m);
         mask &= mask - 1u;
         if (qn > QCAP - 64) {
-          stage_candidates(a, o, q, qn, s_a[w]);
+          stage_candidates<F32>(a, o, q, qn, s_a[w]);
           qn = 0;
         }
       }
       t = tn;
       bp = bpn;
-      B = Bn;
+      rb = rbn;
     }
+    if (!PREF || nch == 0) ar = load_a<F32>(a, head);
     // the queue holds this item's entries only (their A data is in its lanes)
     if (qn) {
-      stage_candidates(a, o, q, qn, s_a[w]);
+      stage_candidates<F32>(a, o, q, qn, s_a[w]);
       qn = 0;
     }
     item = next;
@@ -570,8 +664,14 @@ void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, int items_pe
   const uint32_t items = (ngroups + 3) / 4;
   const uint32_t per_block = WAVES * (uint32_t)std::max(items_per_wave, 1);
   const uint32_t blocks = (items + per_block - 1) / per_block;
-  if (fp32) k_filter<true><<<blocks, MT, 0, s>>>(a, o);
-  else k_filter<false><<<blocks, MT, 0, s>>>(a, o);
+  static const bool pref = std::getenv("HLC_EXP_NOPREF") == nullptr;  // experiment switch (temporary)
+  if (fp32) {
+    if (pref) k_filter<true, true><<<blocks, MT, 0, s>>>(a, o);
+    else k_filter<true, false><<<blocks, MT, 0, s>>>(a, o);
+  } else {
+    if (pref) k_filter<false, true><<<blocks, MT, 0, s>>>(a, o);
+    else k_filter<false, false><<<blocks, MT, 0, s>>>(a, o);
+  }
 }
 
 void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s) {

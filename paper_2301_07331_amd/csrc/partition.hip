@@ -91,18 +91,32 @@ __device__ inline void unit_vector(double ra, double dec, double& x, double& y, 
 }
 
 // Besides the keys, each source's working record is written in input order
-// (coalesced), so the layout after the sort is a single 32-B gather per
-// entry instead of two 8-B gathers of (ra, dec) that each cost a cache line.
+// (coalesced): the FP64 record (unit vector and index, 32 B), or for the
+// FP32 form the 16-B cell record and, in a second array, the FP64 (ra, dec)
+// that certifies candidates. The layout after the sort is then a single
+// gather of one record per entry, from an array a quarter the size of the
+// line traffic of two 8-B gathers of (ra, dec) from the caller's arrays.
 __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
                                                 uint32_t* __restrict__ keys,
                                                 uint32_t* __restrict__ vals, Counters* cnt,
                                                 Rec64* __restrict__ src64,
-                                                SrcRec32* __restrict__ src32) {
+                                                CellRec32* __restrict__ cell32,
+                                                double2* __restrict__ radec32,
+                                                SrcRec32* __restrict__ src32, uint32_t* __restrict__ hist,
+                                                uint32_t hist_tiles, int hist_shift, uint32_t hist_full) {
   __shared__ uint32_t s_w[4];
   __shared__ unsigned long long s_base;
+  __shared__ uint32_t s_h[RS_BINS];
   const uint32_t t = threadIdx.x;
+  // the first radix pass's digit counts of this block's keys, when its radix
+  // tile holds keygen entries only (tiles below hist_full; the others, which
+  // may mix in halo copies, are counted by the pass's own histogram kernel)
+  const uint32_t rtile = (blockIdx.x * KG_TILE) / RS_TILE;
+  const bool count = hist && rtile < hist_full;
+  if (count) s_h[t] = 0u;
+  __syncthreads();
   const uint32_t base = blockIdx.x * KG_TILE;
   uint32_t hkey[KG_ITEMS];
   uint32_t need = 0;  // bit j: item j has a halo copy
@@ -138,9 +152,11 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
       const int32_t z = zone_of(g, d);
       const uint32_t b = bin_of(g, a);
       const uint32_t fr = frac_of(g, a, b);
-      keys[i] = make_key(g, z, b) | fr;
+      const uint32_t key = make_key(g, z, b) | fr;
+      keys[i] = key;
       vals[i] = i;
-      if (src64 || src32) {
+      if (count) atomicAdd(&s_h[(key >> hist_shift) & 0xffu], 1u);
+      if (src64 || cell32 || src32) {
         double x, y, w;
         unit_vector(a, d, x, y, w);
         if (src64) {
@@ -152,12 +168,13 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
           r.pad = 0u;
           src64[i] = r;
         }
+        if (cell32) {
+          cell32[i] = encode_cell(x, y, w);
+          radec32[i] = make_double2(a, d);
+        }
         if (src32) {
           SrcRec32 r;
-          r.x = (float)x;
-          r.y = (float)y;
-          r.z = (float)w;
-          r.idx = i;
+          r.c = encode_cell(x, y, w);
           r.ra = a;
           r.dec = d;
           src32[i] = r;
@@ -176,6 +193,10 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
     }
   }
   if (bad) atomicOr(&cnt->err, err_bit);
+  if (count) {
+    __syncthreads();
+    if (s_h[t]) atomicAdd(&hist[(size_t)t * hist_tiles + rtile], s_h[t]);
+  }
   if (!halo) return;
   uint32_t total;
   const uint32_t off = block_exclusive_scan((uint32_t)__popc(need), &total, s_w);
@@ -199,13 +220,14 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                            DevCount nc, int shift,
                                                            uint32_t* __restrict__ counts,
-                                                           uint32_t ntiles) {
+                                                           uint32_t ntiles, uint32_t tile0) {
   __shared__ uint32_t h[4][RS_BINS];
   const uint32_t n = nc.get();
   const uint32_t t = threadIdx.x, w = t >> 6;
+  const uint32_t tile = tile0 + blockIdx.x;
   for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&h[0][0])[k] = 0u;
   __syncthreads();
-  const uint32_t base = blockIdx.x * RS_TILE;
+  const uint32_t base = tile * RS_TILE;
   // every load in flight before the first use
   uint32_t k[RS_ITEMS];
   if (base + RS_TILE <= n) {
@@ -222,7 +244,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
   for (int j = 0; j < RS_ITEMS; ++j)
     if (base + j * RS_THREADS + t < n) atomicAdd(&h[w][(k[j] >> shift) & 0xffu], 1u);
   __syncthreads();
-  counts[t * ntiles + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+  counts[t * ntiles + tile] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
 // Block d: exclusive scan, in place, of digit d's per-tile counts (tile
@@ -391,6 +413,18 @@ __global__ void k_zone_starts(const uint32_t* __restrict__ keys, DevCount nc, Ge
   zstart[z] = lower_bound_u32(keys, 0, n, make_key(g, z, 0u));
 }
 
+// The same from the coarse key index when a zone's first key is a multiple
+// of the index's step (idx[i] = first position with key >= i << shift).
+__global__ void k_zone_starts_index(const uint32_t* __restrict__ idx, int shift, uint32_t T, DevCount nc, Geom g,
+                                    uint32_t* __restrict__ zstart) {
+  const uint32_t n = nc.get();
+  uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z > (uint32_t)g.nz) return;
+  if (z == (uint32_t)g.nz) { zstart[z] = n; return; }
+  const uint32_t i = make_key(g, (int32_t)z, 0u) >> shift;
+  zstart[z] = i < T ? idx[i] : n;
+}
+
 // ---------------------------------------------------------------------------
 // working layouts
 // ---------------------------------------------------------------------------
@@ -417,27 +451,24 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
   rec[p] = r;
 }
 
-// FP32 unit vector (each component rounded once from FP64) and the FP64
-// (ra, dec) that certifies its candidates
+// FP32 cell record of the FP64 unit vector, from the caller's coordinates
 __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
-                                                  Rec32* __restrict__ rec,
-                                                  double2* __restrict__ radec) {
+                                                  CellRec32* __restrict__ rec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc.get()) return;
-  uint32_t v = vals[p];
-  uint32_t i = v & IDX_MASK;
-  double a = ra[i], d = dec[i];
+  uint32_t i = vals[p] & IDX_MASK;
   double x, y, z;
-  unit_vector(a, d, x, y, z);
-  Rec32 r;
-  r.x = (float)x;
-  r.y = (float)y;
-  r.z = (float)z;
-  r.idx = v;
-  rec[p] = r;
-  radec[p] = make_double2(a, d);
+  unit_vector(ra[i], dec[i], x, y, z);
+  rec[p] = encode_cell(x, y, z);
+}
+
+// (ra, dec) of each source interleaved, in input order
+__global__ __launch_bounds__(256) void k_interleave(const double* __restrict__ ra, const double* __restrict__ dec,
+                                                    uint32_t n, double2* __restrict__ radec) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) radec[i] = make_double2(ra[i], dec[i]);
 }
 
 // Sorted working records from the per-source records of the keygen.
@@ -452,21 +483,15 @@ __global__ __launch_bounds__(256) void k_gather64(const uint32_t* __restrict__ v
   rec[p] = r;
 }
 
+// Sorted FP32 cell records from the keygen's (16 B each: the gathered array
+// is half the size of the FP64 form's, so more of it stays in the device's
+// last-level cache between the reads of one 128-B line's eight records).
 __global__ __launch_bounds__(256) void k_gather32(const uint32_t* __restrict__ vals, DevCount nc,
-                                                  const SrcRec32* __restrict__ src,
-                                                  Rec32* __restrict__ rec,
-                                                  double2* __restrict__ radec) {
+                                                  const CellRec32* __restrict__ src,
+                                                  CellRec32* __restrict__ rec) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc.get()) return;
-  const uint32_t v = vals[p];
-  const SrcRec32 r = src[v & IDX_MASK];
-  Rec32 o;
-  o.x = r.x;
-  o.y = r.y;
-  o.z = r.z;
-  o.idx = v;
-  rec[p] = o;
-  radec[p] = make_double2(r.ra, r.dec);
+  rec[p] = src[vals[p] & IDX_MASK];
 }
 
 // ---------------------------------------------------------------------------
@@ -986,10 +1011,22 @@ void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64,
 
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
-                   Rec64* src64, SrcRec32* src32) {
+                   Rec64* src64, CellRec32* cell32, double2* radec32, SrcRec32* src32, const KeygenHist* kh) {
   if (n == 0) return;
+  uint32_t* hist = nullptr;
+  uint32_t tiles = 0, full = 0;
+  int shift = 0;
+  if (kh) {
+    tiles = cdiv(kh->cap, RS_TILE);
+    full = n / RS_TILE;
+    shift = kh->shift;
+    hist = full ? kh->counts : nullptr;
+    if (hist) k_fill_u32<<<std::min<uint32_t>(cdiv((size_t)RS_BINS * tiles, 256), 4096), 256, 0, s>>>(
+        kh->counts, 0u, (size_t)RS_BINS * tiles);
+  }
   k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys,
-                                                                    vals, cnt, src64, src32);
+                                                                    vals, cnt, src64, cell32,
+                                                                    radec32, src32, hist, tiles, shift, full);
 }
 
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s) {
@@ -997,10 +1034,10 @@ void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, 
   k_gather64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
 }
 
-void launch_gather32(const uint32_t* vals, const DevCount& n, const SrcRec32* src, Rec32* rec, double2* radec,
+void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* src, CellRec32* rec,
                      hipStream_t s) {
   if (n.cap == 0) return;
-  k_gather32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec, radec);
+  k_gather32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
 }
 
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
@@ -1008,8 +1045,10 @@ size_t sort_digit_totals_len(uint32_t n) { (void)n; return RS_BINS; }
 
 int radix_passes(int key_bits, int lo_bit) { return (key_bits - lo_bit + 7) / 8; }
 
+uint32_t keygen_hist_tiles(uint32_t n) { return n / RS_TILE; }
+
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt, int lo_bit) {
+                hipStream_t s, bool from_alt, int lo_bit, uint32_t hist_done) {
   const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
   const int passes = radix_passes(key_bits, lo_bit);
   uint32_t *kin = keys, *vin = vals, *kout = sc.keys_alt, *vout = sc.vals_alt;
@@ -1021,7 +1060,9 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bit
     const uint32_t ntiles = cdiv(n, RS_TILE);
     for (int p = 0; p < passes; ++p) {
       const int shift = lo_bit + 8 * p;
-      k_radix_hist<<<ntiles, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles);
+      // the first pass's counts of tiles below hist_done came from the keygen
+      const uint32_t h0 = p == 0 ? std::min(hist_done, ntiles) : 0u;
+      if (h0 < ntiles) k_radix_hist<<<ntiles - h0, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles, h0);
       k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
       k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts,
                                                     sc.digit_totals, ntiles);
@@ -1061,6 +1102,11 @@ void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream
   k_zone_tables<<<cdiv((uint32_t)g.nz, 256), 256, 0, s>>>(g, zmarg, zdelta);
 }
 
+void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const DevCount& n, const Geom& g,
+                              uint32_t* zstart, hipStream_t s) {
+  k_zone_starts_index<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(idx, shift, T, n, g, zstart);
+}
+
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s) {
   k_zone_starts<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(keys, n, g, zstart);
@@ -1073,9 +1119,14 @@ void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, 
 }
 
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     Rec32* rec, double2* radec, hipStream_t s) {
+                     CellRec32* rec, hipStream_t s) {
   if (n.cap == 0) return;
-  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec, radec);
+  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
+}
+
+void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s) {
+  if (n == 0) return;
+  k_interleave<<<cdiv(n, 256), 256, 0, s>>>(ra, dec, n, radec);
 }
 
 size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap) { return (size_t)cdiv(na_cap + nb_cap, MP_TILE) + 1; }

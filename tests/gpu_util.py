@@ -38,3 +38,42 @@ def assert_same(keys, sep, ref, tol=SEP_TOL_ARCSEC, label=""):
         err = np.abs(sep - ref.sep)
         assert err.max() <= tol, f"{label}: max |dsep| = {err.max():.3e} arcsec"
     return len(keys)
+
+
+def sorted_on_gpu(pairs, sep):
+    """Pair keys (a << 32 | b) sorted on the GPU, with the separations in the
+    same order, both returned as numpy (for results of 1e8 pairs and more).
+    pairs: (n, 2) uint32 numpy array or an (n, 2) int32 device tensor."""
+    import torch
+    if isinstance(pairs, np.ndarray):
+        p = torch.from_numpy(pairs.view(np.int32)).to("cuda")
+    else:
+        p = pairs
+    a = p[:, 0].to(torch.int64) & 0xFFFFFFFF
+    b = p[:, 1].to(torch.int64) & 0xFFFFFFFF
+    keys = (a << 32) | b
+    del a, b
+    k, order = torch.sort(keys)
+    del keys
+    s = torch.as_tensor(sep).to("cuda")[order] if sep is not None else None
+    out_k = k.cpu().numpy().view(np.uint64)
+    out_s = s.cpu().numpy() if s is not None else None
+    del k, order, s
+    torch.cuda.empty_cache()
+    return out_k, out_s
+
+
+def assert_same_sorted(keys, sep, ref_keys, ref_sep, tol=SEP_TOL_ARCSEC, label=""):
+    """assert_same for large results whose keys are already sorted (linear-time checks)."""
+    assert len(keys) < 2 or not np.any(keys[1:] == keys[:-1]), f"{label}: duplicate pairs"
+    if len(keys) != len(ref_keys) or not np.array_equal(keys, ref_keys):
+        extra = np.setdiff1d(keys, ref_keys)
+        missing = np.setdiff1d(ref_keys, keys)
+        raise AssertionError(f"{label}: {len(keys)} vs oracle {len(ref_keys)}; extra {len(extra)} "
+                             f"e.g. {[(int(k >> 32), int(k & 0xffffffff)) for k in extra[:5]]}; "
+                             f"missing {len(missing)} e.g. "
+                             f"{[(int(k >> 32), int(k & 0xffffffff)) for k in missing[:5]]}")
+    if sep is not None and len(sep):
+        err = float(np.max(np.abs(sep - ref_sep)))
+        assert err <= tol, f"{label}: max |dsep| = {err:.3e} arcsec"
+    return len(keys)

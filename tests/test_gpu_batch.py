@@ -89,6 +89,52 @@ def test_batch_mixed_jobs(hlc, prec):
         _compare(k, s, c, ref, f"mixed tuning={tuning}")
 
 
+def test_batch_every_tuning_candidate(hlc):
+    """Every configuration the batched autotuner can choose (zone-height factor
+    x partition tile x match blocks per compute unit), each run against the
+    oracle; then the autotuned call, whose choice is reported in the stats."""
+    jobs, cat = _mixed_batch()
+    ref = _oracle_batch(jobs, *cat)
+    arrs = [to_dev(x) for x in cat]
+    cap = len(ref[0]) + 1000
+    factors, tiles, grids = (0.35, 0.5, 0.7, 1.0, 1.4, 2.0, 2.8), (256, 512, 1024, 2048), (1, 2, 4, 8)
+    n = 0
+    for f in factors:
+        for t in tiles:
+            for g in grids:
+                tu = {"zone_height_factor": f, "batch_tile": t, "batch_blocks_per_cu": g}
+                k, s, c = _run(hlc, jobs, arrs, 0, cap, tu)
+                _compare(k, s, c, ref, f"fp32 {tu}")
+                st = hlc.last_stats()
+                assert (st["batch_tile"], st["batch_blocks_per_cu"]) == (t, g)
+                n += 1
+    # the FP64 filter over each knob's candidates, the others at their defaults
+    for tu in ([{"zone_height_factor": f} for f in factors] + [{"batch_tile": t} for t in tiles] +
+               [{"batch_blocks_per_cu": g} for g in grids]):
+        k, s, c = _run(hlc, jobs, arrs, 1, cap, tu)
+        _compare(k, s, c, ref, f"fp64 {tu}")
+        n += 1
+    for prec in (0, 1):
+        k, s, c = _run(hlc, jobs, arrs, prec, cap, None)
+        _compare(k, s, c, ref, f"autotuned prec={prec}")
+        st = hlc.last_stats()
+        assert st["zone_height_arcsec"] in factors and st["batch_tile"] in tiles
+        assert st["batch_blocks_per_cu"] in grids
+        print("autotuned", prec, st["zone_height_arcsec"], st["batch_tile"], st["batch_blocks_per_cu"], flush=True)
+    print("configurations compared with the oracle:", n + 2, flush=True)
+
+
+def test_batch_tuning_errors(hlc):
+    jobs, cat = _mixed_batch()
+    arrs = [to_dev(x) for x in cat]
+    import torch
+    out = torch.empty((16, 2), dtype=torch.int32, device="cuda")
+    sep = torch.empty(16, dtype=torch.float64, device="cuda")
+    for tu in ({"batch_tile": 300}, {"batch_blocks_per_cu": 9}, {"batch_blocks_per_cu": -1}):
+        st, _ = hlc.hlc_xmatch_batch(jobs, *arrs, out, sep, tuning=tu)
+        assert st == hlc.HLC_E_INVAL, tu
+
+
 def test_batch_graph_replay(hlc):
     """Replays of the captured graph, with eager work in between, match the first result."""
     import torch

@@ -81,31 +81,33 @@ def test_stream_several_slabs_full_oracle(hlc, prec):
     assert_same(k[o], sep[o], ref, label=f"slabs prec={prec}")
 
 
-def test_stream_large_400M_x_100M_sampled(hlc):
-    """The large workload at full size: every pair of a random sample of A sources checked."""
+@pytest.mark.timeout(1200)
+def test_stream_large_400M_x_100M_full(hlc):
+    """The large workload at full size, both precisions: every pair and separation
+    against the oracle's whole join (the exact result is the completeness reference,
+    as the paper's section 5.3 takes the exact serial result)."""
     import time
+    from tests.gpu_util import assert_same_sorted, sorted_on_gpu
     t0 = time.time()
     c = synth.large_pair()
     print(f"generated in {time.time() - t0:.1f}s", flush=True)
+    arrs = [_pinned(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+    got = {}
+    for prec in (0, 1):
+        t0 = time.time()
+        pairs, sep = hlc.xmatch_stream(*arrs, c.r_arcsec, precision=prec, ring_pairs=1 << 26)
+        print(f"precision {prec}: streamed {len(pairs)} pairs in {time.time() - t0:.1f}s", flush=True)
+        got[prec] = sorted_on_gpu(pairs, sep)
+        del pairs, sep
+    del arrs
     t0 = time.time()
-    pairs, sep = hlc.xmatch_stream(_pinned(c.a_ra), _pinned(c.a_dec), _pinned(c.b_ra), _pinned(c.b_dec),
-                                   c.r_arcsec, precision=0, ring_pairs=1 << 26)
-    print(f"streamed {len(pairs)} pairs in {time.time() - t0:.1f}s", flush=True)
-    assert np.all(sep <= c.r_arcsec) and np.all(sep >= 0)
-    k = _keys(pairs)
-    assert len(np.unique(k)) == len(k)
-    g = np.random.default_rng(1)
-    sample = np.sort(g.choice(c.na, size=200_000, replace=False))
-    ref = oracle.xmatch(c.a_ra[sample], c.a_dec[sample], c.b_ra, c.b_dec, c.r_arcsec)
-    ref_keys = (sample[ref.a].astype(np.uint64) << np.uint64(32)) | ref.b.astype(np.uint64)
-    mine = np.isin(pairs[:, 0], sample)
-    got = k[mine]
-    o = np.argsort(got)
-    ro = np.argsort(ref_keys)
-    assert np.array_equal(got[o], ref_keys[ro])
-    assert np.max(np.abs(sep[mine][o] - ref.sep[ro])) <= 1e-9
-    # counterpart + chance expectation of the recipe (Appendix-style arithmetic)
-    assert 1.0e8 < len(pairs) < 1.3e8
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    print(f"oracle: {len(ref)} pairs in {time.time() - t0:.1f}s", flush=True)
+    ref_keys = ref.keys()
+    for prec in (0, 1):
+        keys, sep = got[prec]
+        n = assert_same_sorted(keys, sep, ref_keys, ref.sep, label=f"400M x 100M prec={prec}")
+        print(f"precision {prec}: {n} pairs identical to the oracle", flush=True)
 
 
 def test_transfer_model_fit(hlc):

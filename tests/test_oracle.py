@@ -354,6 +354,34 @@ def test_healpix_base_faces():
     assert oracle.hp_nest(0, 10.0, 90.0) == 0 and oracle.hp_nest(0, 10.0, -90.0) == 8
 
 
+def test_healpix_in_face_orientation():
+    """Order 1: each base face splits into four sub-pixels numbered, in the
+    nested scheme's Z order, from the face's southern corner (0) through its
+    eastern (1) and western (2) corners to its northern corner (3); the
+    in-face x axis runs from the southern towards the eastern corner, y
+    towards the western one (Gorski et al. 2005, the nested numbering). The
+    points sit well inside one sub-pixel each, placed from the faces' corner
+    positions alone: an equatorial face's corners are at Dec -/+ asin(2/3)
+    on its central meridian and at Dec 0, 45 deg east and west of it; a north
+    polar face's at (its meridian, Dec 0), 45 deg east and west of it at
+    Dec asin(2/3), and the pole; a south polar face's mirror those.
+    Transposing or mirroring the in-face axes swaps east and west, or north
+    and south."""
+    cases = [
+        # face 4: equatorial, centred on RA 0
+        (4, (0.0, -30.0), (30.0, 0.0), (330.0, 0.0), (0.0, 30.0)),
+        # face 6: equatorial, centred on RA 180
+        (6, (180.0, -30.0), (210.0, 0.0), (150.0, 0.0), (180.0, 30.0)),
+        # face 0: north polar, centred on RA 45 (southern corner at RA 45, Dec 0)
+        (0, (45.0, 15.0), (75.0, 40.0), (15.0, 40.0), (45.0, 70.0)),
+        # face 9: south polar, centred on RA 135 (northern corner at RA 135, Dec 0)
+        (9, (135.0, -70.0), (165.0, -40.0), (105.0, -40.0), (135.0, -15.0)),
+    ]
+    for face, south, east, west, north in cases:
+        got = [oracle.hp_nest(1, ra, dec) for ra, dec in (south, east, west, north)]
+        assert got == [4 * face + k for k in range(4)], (face, got)
+
+
 def test_healpix_nesting_and_range():
     """Nested scheme: the parent of a pixel at order k+1 is its index >> 2 at order k."""
     g = synth.rng(930, 0)

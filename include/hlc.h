@@ -145,6 +145,25 @@ int hlc_xmatch(const double *a_ra, const double *a_dec, int64_t na, const double
                const double *b_dec, int64_t nb, double r_arcsec, hlc_pair *out_pairs,
                double *out_sep_arcsec, const hlc_opts *opts);
 
+/* hlc_xmatch for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The same pair set and
+ * separations as hlc_xmatch, from the same kernels, but the call's workspace
+ * and device counters lie in a fixed device array of the library (128 MiB on
+ * each device it runs on, held from the library's load until the process
+ * ends), so the call allocates nothing (no hipMalloc, hipFree, hipHostMalloc,
+ * no stream or event creation). Every kernel runs on opts->stream; the call
+ * returns once the pair count is known. Limits: a call whose workspace would
+ * not fit the array (roughly beyond 500,000 sources per catalogue, fewer when
+ * the pairs or near-threshold candidates are many) returns HLC_E_UNSUPPORTED,
+ * as do HLC_SELF, HLC_SORTED, HLC_PROFILE and HLC_TIME_FILTER. Every call on one device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one device (two host threads, or two streams) race and must be
+ * serialised by the caller. Arguments, outputs and other errors as
+ * hlc_xmatch.                                                              */
+int hlc_xmatch_noalloc(const double *a_ra, const double *a_dec, int64_t na, const double *b_ra,
+                       const double *b_dec, int64_t nb, double r_arcsec, hlc_pair *out_pairs,
+                       double *out_sep_arcsec, const hlc_opts *opts);
+
 /* Eq. (4) with per-source error radii: report (i, j) iff the separation is
  * at most k_sigma * sqrt(a_err[i]^2 + b_err[j]^2) arcsec (the paper uses
  * k_sigma = 3). a_err [na], b_err [nb]: device FP64 arcsec, finite, >= 0.

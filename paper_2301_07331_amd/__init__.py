@@ -17,7 +17,7 @@ HLC_OK, HLC_E_INVAL, HLC_E_NOMEM, HLC_E_OVERFLOW, HLC_E_DEVICE, HLC_E_UNSUPPORTE
 HLC_FP32_RECHECK, HLC_FP64 = 0, 1
 HLC_NO_SEP, HLC_PROFILE, HLC_SORTED, HLC_SELF, HLC_TIME_FILTER = 0x1, 0x2, 0x4, 0x8, 0x10
 
-EXPORTS = ["hlc_xmatch", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
+EXPORTS = ["hlc_xmatch", "hlc_xmatch_noalloc", "hlc_xmatch_radii", "hlc_xmatch_quad", "hlc_partition", "hlc_part_free", "hlc_xmatch_part", "hlc_xmatch_batch",
            "hlc_xmatch_stream", "hlc_transfer_model", "hlc_strerror", "hlc_last_stats", "hlc_shutdown"]
 
 
@@ -75,6 +75,8 @@ def load() -> C.CDLL:
         vp, i64 = C.c_void_p, C.c_int64
         lib.hlc_xmatch.restype = C.c_int
         lib.hlc_xmatch.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, vp, vp, C.POINTER(hlc_opts)]
+        lib.hlc_xmatch_noalloc.restype = C.c_int
+        lib.hlc_xmatch_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, C.c_double, vp, vp, C.POINTER(hlc_opts)]
         lib.hlc_xmatch_radii.restype = C.c_int
         lib.hlc_xmatch_radii.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp, vp,
                                          C.POINTER(hlc_opts)]
@@ -166,6 +168,19 @@ def hlc_xmatch(a_ra, a_dec, b_ra, b_dec, r_arcsec, out_pairs, out_sep, *, precis
     o, n, tu = make_opts(precision, capacity, stream, flags, tuning)
     st = load().hlc_xmatch(_ptr(a_ra), _ptr(a_dec), a_ra.numel(), _ptr(b_ra), _ptr(b_dec), b_ra.numel(),
                            float(r_arcsec), _ptr(out_pairs), _ptr(out_sep), C.byref(o))
+    return st, n.value
+
+
+def hlc_xmatch_noalloc(a_ra, a_dec, b_ra, b_dec, r_arcsec, out_pairs, out_sep, *, precision=HLC_FP32_RECHECK,
+                       capacity=None, stream=None, flags=0, tuning=None):
+    """Call hlc_xmatch_noalloc (no allocation inside the library) on torch CUDA
+    tensors. Returns (status, n_pairs); arguments as hlc_xmatch."""
+    _check_coords(a_ra, a_dec, b_ra, b_dec)
+    if capacity is None:
+        capacity = 0 if out_pairs is None else out_pairs.shape[0]
+    o, n, tu = make_opts(precision, capacity, stream, flags, tuning)
+    st = load().hlc_xmatch_noalloc(_ptr(a_ra), _ptr(a_dec), a_ra.numel(), _ptr(b_ra), _ptr(b_dec), b_ra.numel(),
+                                   float(r_arcsec), _ptr(out_pairs), _ptr(out_sep), C.byref(o))
     return st, n.value
 
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlc.so")
 SOURCES = ["partition.hip", "match.hip", "stream.hip", "batch.hip", "context.hip", "geometry.hip",
-           "pipeline.hip", "xmatch_api.hip", "part_api.hip", "batch_api.hip", "tune_cache.hip", "stream_api.hip"]
+           "pipeline.hip", "xmatch_api.hip", "part_api.hip", "batch_api.hip", "tune_cache.hip", "stream_api.hip",
+           "noalloc_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

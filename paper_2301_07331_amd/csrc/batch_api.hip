@@ -344,6 +344,29 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
   if (g_factor) cfg.factor = tu->zone_height_factor;
   if (g_tile) cfg.tile = tu->batch_tile;
   if (g_bpc) cfg.bpc = tu->batch_blocks_per_cu;
+  const bool fp32 = o->precision == HLC_FP32_RECHECK;
+  // the cache bucket: precision, device, size class (from the job totals, so
+  // that the plan is built once, for the tile the call will use)
+  int64_t tot_a = 0, tot_b = 0;
+  for (int32_t j = 0; j < njobs; ++j) {
+    tot_a += std::max<int64_t>(jobs[j].na, 0);
+    tot_b += std::max<int64_t>(jobs[j].nb, 0);
+  }
+  char size_class[96];
+  std::snprintf(size_class, sizeof size_class, "|j%d|a%d|b%d", ceil_log2((uint64_t)njobs),
+                ceil_log2((uint64_t)tot_a), ceil_log2((uint64_t)tot_b));
+  const std::string bucket = std::string("batch|") + (fp32 ? "fp32|" : "fp64|") + tune_device_tag() + size_class;
+  bool tune = !(g_factor && g_tile && g_bpc);
+  if (tune) {
+    std::vector<double> v;
+    if (tune_lookup(bucket, &v) && v.size() >= 3 && v[0] > 0 && batch_tile_ok((int)v[1]) && v[2] >= 1 &&
+        v[2] <= 8) {
+      if (!g_factor) cfg.factor = v[0];
+      if (!g_tile) cfg.tile = (int)v[1];
+      if (!g_bpc) cfg.bpc = (int)v[2];
+      tune = false;
+    }
+  }
   HLC_CHECK(ensure_plan(BS, jobs, njobs, cfg.tile));
   const BatchPlan& P0 = BS.plan;
   if ((P0.NA > 0 && (!a_ra || !a_dec)) || (P0.NB > 0 && (!b_ra || !b_dec))) return HLC_E_INVAL;
@@ -378,29 +401,12 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
   HLC_TRY(hipEventRecord(BS.ev_in, us));
   HLC_TRY(hipStreamWaitEvent(BS.st, BS.ev_in, 0));
   hipStream_t s = BS.st;
-  const bool fp32 = o->precision == HLC_FP32_RECHECK;
 
   unsigned long long* jcount = reinterpret_cast<unsigned long long*>(job_pair_count);
   const uint64_t cap = (uint64_t)o->capacity;
   Caps caps = initial_caps(*dev, (uint64_t)(P0.NA + P0.NB), cap, false);
   double* sep = (o->flags & HLC_NO_SEP) ? nullptr : out_sep;
 
-  // the cache bucket: precision, device, size class
-  char size_class[96];
-  std::snprintf(size_class, sizeof size_class, "|j%d|a%d|b%d", ceil_log2((uint64_t)njobs), ceil_log2(P0.NA),
-                ceil_log2(P0.NB));
-  const std::string bucket = std::string("batch|") + (fp32 ? "fp32|" : "fp64|") + tune_device_tag() + size_class;
-  bool tune = !(g_factor && g_tile && g_bpc);
-  if (tune) {
-    std::vector<double> v;
-    if (tune_lookup(bucket, &v) && v.size() >= 3 && v[0] > 0 && batch_tile_ok((int)v[1]) && v[2] >= 1 &&
-        v[2] <= 8) {
-      if (!g_factor) cfg.factor = v[0];
-      if (!g_tile) cfg.tile = (int)v[1];
-      if (!g_bpc) cfg.bpc = (int)v[2];
-      tune = false;
-    }
-  }
   for (int attempt = 0; attempt < 3; ++attempt) {
     BatchBufs b;
     Carve sz{nullptr};

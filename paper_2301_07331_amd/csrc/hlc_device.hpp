@@ -225,6 +225,35 @@ __host__ __device__ inline bool same_zone(const Geom& g, uint32_t ka, uint32_t k
 }
 
 // ---------------------------------------------------------------------------
+// sin and cos of r, |r| <= pi/4, from their Taylor series through r^17 and
+// r^16 in Horner form (the omitted terms are below 2^-62 and 2^-58 of the
+// results). Every step is one explicit FMA or product, so the rounding is
+// the same wherever the sequence is replayed; the error is below 1.5 ulp
+// (checked against a 60-digit evaluation of the same arguments on the CPU).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void sincos_small(double r, double* s, double* c) {
+  const double z = r * r;
+  double ps = 1.0 / 355687428096000.0;  // 1/17!
+  ps = fma(ps, z, -1.0 / 1307674368000.0);
+  ps = fma(ps, z, 1.0 / 6227020800.0);
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  *s = fma(ps, z * r, r);
+  double pc = 1.0 / 20922789888000.0;  // 1/16!
+  pc = fma(pc, z, -1.0 / 87178291200.0);
+  pc = fma(pc, z, 1.0 / 479001600.0);
+  pc = fma(pc, z, -1.0 / 3628800.0);
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  pc = fma(pc, z, -0.5);
+  *c = fma(pc, z, 1.0);
+}
+
+// ---------------------------------------------------------------------------
 // sin and cos of an angle in degrees, |x| <= 360.
 // The argument is reduced by the nearest multiple of 90 degrees, which is
 // exact in FP64 for |x| <= 360 (Sterbenz), converted to radians with a
@@ -237,7 +266,7 @@ __device__ inline void sincos_deg(double x, double* s, double* c) {
   double e = fma(y, DEG2RAD_HI, -p);
   double r = p + fma(y, DEG2RAD_LO, e);
   double sr, cr;
-  sincos(r, &sr, &cr);
+  sincos_small(r, &sr, &cr);
   int qi = ((int)q) & 3;
   if (qi == 0) { *s = sr; *c = cr; }
   else if (qi == 1) { *s = cr; *c = -sr; }

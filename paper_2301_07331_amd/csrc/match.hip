@@ -34,10 +34,11 @@
 //     to the band list.
 //
 // FP64 chord error budget (u = 2^-53): each unit-vector component is a
-// product of two degree-reduced sin/cos values (each within ~1.5 ulp) and has
-// an absolute error <= 4u; a chord component then errs by <= 8u + u|d|, so
-// |chord_fp64 - chord| <= sqrt(3)*8u + u*chord ~= 1.6e-15. ETA64 = 4e-15 is
-// used for the thresholds (2.5x margin for the device libm).
+// product of two degree-reduced sin/cos values (each within 1.5 ulp: the
+// Taylor-series evaluation of sincos_small) and has an absolute error <= 4u;
+// a chord component then errs by <= 8u + u|d|, so |chord_fp64 - chord| <=
+// sqrt(3)*8u + u*chord ~= 1.6e-15. ETA64 = 4e-15 is used for the thresholds
+// (a 2.5x margin).
 //
 // FP32 filter budget (v = 2^-24 the FP32 unit roundoff, w = 2^-34 the cell
 // unit). A record's stored position p lies below the FP64 unit vector by
@@ -432,10 +433,10 @@ __device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
 
 // Persistent: wave w of W takes items w, w + W, ... (an item is four groups,
 // one per 16-lane row). The next item's ranges and A index are loaded
-// while the current one is tested, and its A records once the first chunk
-// has been tested (A's records are read in place, one cache line each).
-template <bool F32, bool PREF>
-__global__ __launch_bounds__(MT, PREF ? 1 : 7) void k_filter(MatchArgs a, OutArgs o) {
+// while the current one is tested, and its A records once the current one's
+// chunks are done (their loads then overlap the drain of the queue).
+template <bool F32>
+__global__ __launch_bounds__(MT, 7) void k_filter(MatchArgs a, OutArgs o) {
   using V = typename std::conditional<F32, float, double>::type;
   __shared__ uint2 s_q[WAVES][QCAP];
   __shared__ ALane s_a[WAVES][64];
@@ -522,8 +523,6 @@ __global__ __launch_bounds__(MT, PREF ? 1 : 7) void k_filter(MatchArgs a, OutArg
       const uint32_t nmax = min(tmax - 16u * c, (uint32_t)GROUP);
       uint32_t mask = 0u;
       tests<0, V>(A, B, thr, nmax, mask);
-      // the next item's A records, once its index has arrived
-      if (PREF && c == 0) ar = load_a<F32>(a, head);
       // drain the hits into the queue, lowest bit first
       while (__ballot(mask != 0u)) {
         const bool has = mask != 0u;
@@ -542,7 +541,7 @@ __global__ __launch_bounds__(MT, PREF ? 1 : 7) void k_filter(MatchArgs a, OutArg
       bp = bpn;
       rb = rbn;
     }
-    if (!PREF || nch == 0) ar = load_a<F32>(a, head);
+    ar = load_a<F32>(a, head);
     // the queue holds this item's entries only (their A data is in its lanes)
     if (qn) {
       stage_candidates<F32>(a, o, q, qn, s_a[w]);
@@ -664,14 +663,8 @@ void launch_filter(const MatchArgs& a, const OutArgs& o, bool fp32, int items_pe
   const uint32_t items = (ngroups + 3) / 4;
   const uint32_t per_block = WAVES * (uint32_t)std::max(items_per_wave, 1);
   const uint32_t blocks = (items + per_block - 1) / per_block;
-  static const bool pref = std::getenv("HLC_EXP_NOPREF") == nullptr;  // experiment switch (temporary)
-  if (fp32) {
-    if (pref) k_filter<true, true><<<blocks, MT, 0, s>>>(a, o);
-    else k_filter<true, false><<<blocks, MT, 0, s>>>(a, o);
-  } else {
-    if (pref) k_filter<false, true><<<blocks, MT, 0, s>>>(a, o);
-    else k_filter<false, false><<<blocks, MT, 0, s>>>(a, o);
-  }
+  if (fp32) k_filter<true><<<blocks, MT, 0, s>>>(a, o);
+  else k_filter<false><<<blocks, MT, 0, s>>>(a, o);
 }
 
 void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s) {

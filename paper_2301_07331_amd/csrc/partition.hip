@@ -603,22 +603,55 @@ __device__ inline uint32_t gallop_upper(const uint32_t* keys, uint32_t K, uint32
 
 // Coarse index of sorted keys: idx[i] = first position with key >= i << shift,
 // for i < T (T = (key space >> shift) + 1).
-__global__ void k_key_index(const uint32_t* __restrict__ keys, DevCount nc, int shift, uint32_t T,
-                            uint32_t* __restrict__ idx) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T) return;
+// Built by one pass over the sorted keys: position p is the entry
+// of every index slot i with key[p - 1] >> shift < i <= key[p] >> shift
+// (slots from 0 for p = 0, up to T - 1 for p = n), so every slot is written
+// exactly once. Short runs of slots are written by their lane, long ones
+// (empty stretches of key space) by the whole wave.
+constexpr uint32_t KI_PER = 4;  // positions per thread
+
+__global__ __launch_bounds__(256) void k_key_index_scan(const uint32_t* __restrict__ keys, DevCount nc, int shift,
+                                                        uint32_t T, uint32_t* __restrict__ idx) {
   const uint32_t n = nc.get();
-  const uint64_t K = (uint64_t)i << shift;
-  uint32_t lo = 0, hi = n;
-  if (K > 0xffffffffull) {
-    lo = n;
+  const uint32_t p0 = (blockIdx.x * blockDim.x + threadIdx.x) * KI_PER;
+  const uint32_t lane = threadIdx.x & 63u;
+  // keys p0 - 1 .. p0 + KI_PER - 1 (one 16-B load when all are present)
+  uint32_t k[KI_PER];
+  uint32_t prev = 0u;
+  if (p0 + KI_PER <= n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(keys + p0);
+    k[0] = v.x;
+    k[1] = v.y;
+    k[2] = v.z;
+    k[3] = v.w;
   } else {
-    while (lo < hi) {
-      const uint32_t mid = lo + ((hi - lo) >> 1);
-      if (keys[mid] < (uint32_t)K) lo = mid + 1; else hi = mid;
+#pragma unroll
+    for (uint32_t q = 0; q < KI_PER; ++q) k[q] = p0 + q < n ? keys[p0 + q] : 0u;
+  }
+  if (p0 > 0 && p0 <= n) prev = keys[p0 - 1];
+#pragma unroll
+  for (uint32_t q = 0; q < KI_PER; ++q) {
+    const uint32_t p = p0 + q;
+    uint32_t lo = 0u, hi = 0u;  // slots [lo, hi) get p
+    if (p <= n) {
+      lo = p == 0 ? 0u : (prev >> shift) + 1u;
+      hi = p == n ? T : min((k[q] >> shift) + 1u, T);
+      if (hi < lo) hi = lo;
+    }
+    prev = k[q];
+    constexpr uint32_t SHORT = 4;
+    const bool is_long = hi - lo > SHORT;
+    if (!is_long)
+      for (uint32_t i = lo; i < hi; ++i) idx[i] = p;
+    uint64_t longs = __ballot(is_long);
+    while (longs) {
+      const int l = __builtin_ctzll(longs);
+      longs &= longs - 1ull;
+      const uint32_t L0 = (uint32_t)__shfl((int)lo, l), L1 = (uint32_t)__shfl((int)hi, l);
+      const uint32_t P = (uint32_t)__shfl((int)p, l);
+      for (uint32_t i = L0 + lane; i < L1; i += 64u) idx[i] = P;
     }
   }
-  idx[i] = lo;
 }
 
 // First position in [lo, hi) whose key is >= K (hi if none), searched only
@@ -634,6 +667,40 @@ __device__ inline uint32_t index_lower(const uint32_t* keys, const uint32_t* idx
     if (keys[mid] < (uint32_t)K) l = mid + 1; else r = mid;
   }
   return l;
+}
+
+// index_lower of two keys at once: the two searches advance in lockstep, so
+// each step's two loads are in flight together (keys[0] stands in for a
+// finished search: every key buffer holds at least one entry)
+__device__ inline void index_lower2(const uint32_t* keys, const uint32_t* idx, int shift, uint32_t T,
+                                    uint64_t K1, uint64_t K2, uint32_t lo, uint32_t hi, uint32_t& r1,
+                                    uint32_t& r2) {
+  auto bracket = [&](uint64_t K, uint32_t& l, uint32_t& r) {
+    const uint64_t i = K >> shift;
+    if (i + 1 >= T) {
+      l = r = hi;
+      return;
+    }
+    l = max(lo, idx[i]);
+    r = min(hi, idx[i + 1]);
+    if (l > r) l = r;
+  };
+  uint32_t l1, h1, l2, h2;
+  bracket(K1, l1, h1);
+  bracket(K2, l2, h2);
+  while (l1 < h1 || l2 < h2) {
+    const bool a1 = l1 < h1, a2 = l2 < h2;
+    const uint32_t m1 = l1 + ((h1 - l1) >> 1), m2 = l2 + ((h2 - l2) >> 1);
+    const uint32_t k1 = keys[a1 ? m1 : 0u], k2 = keys[a2 ? m2 : 0u];
+    if (a1) {
+      if (k1 < (uint32_t)K1) l1 = m1 + 1; else h1 = m1;
+    }
+    if (a2) {
+      if (k2 < (uint32_t)K2) l2 = m2 + 1; else h2 = m2;
+    }
+  }
+  r1 = l1;
+  r2 = l2;
 }
 
 // One thread per group of GROUP consecutive sorted A entries; the group's
@@ -727,12 +794,15 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
       L.add(zs, ze);
     } else if (zs < ze) {
       auto lower = [&](uint64_t K) { return index_lower(keysB, kidx, kshift, kT, K, zs, ze); };
-      uint32_t s = lower((uint64_t)make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)) + (lo < 0 ? 0u : flo));
       // (the end of a cell: its last key + 1 = the first key of the next;
       // with sorted sub-bin bits, the edge's own key + 1)
       const uint64_t cell = 1ull << g.fb;
-      uint32_t e = lower((uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) +
-                         (hi > nbins - 1 ? cell : (uint64_t)fhi + 1u));
+      uint32_t s, e;
+      index_lower2(keysB, kidx, kshift, kT,
+                   (uint64_t)make_key(g, z, (uint32_t)(lo < 0 ? 0 : lo)) + (lo < 0 ? 0u : flo),
+                   (uint64_t)make_key(g, z, (uint32_t)(hi > nbins - 1 ? nbins - 1 : hi)) +
+                       (hi > nbins - 1 ? cell : (uint64_t)fhi + 1u),
+                   zs, ze, s, e);
       if (hi > nbins - 1) {  // window passes RA 360: low bins of the zone
         uint32_t e2 = lower((uint64_t)make_key(g, z, (uint32_t)(hi - nbins)) + (uint64_t)fhi + 1u);
         L.add(zs, e2);
@@ -1141,7 +1211,7 @@ void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* 
 
 void launch_key_index(const uint32_t* keys, const DevCount& n, int shift, uint32_t T, uint32_t* idx,
                       hipStream_t s) {
-  k_key_index<<<cdiv(T, 256), 256, 0, s>>>(keys, n, shift, T, idx);
+  k_key_index_scan<<<cdiv(cdiv((uint64_t)n.cap + 1, KI_PER), 256), 256, 0, s>>>(keys, n, shift, T, idx);
 }
 
 void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* kidx, int kshift, uint32_t kT,

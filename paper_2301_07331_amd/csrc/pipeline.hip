@@ -224,10 +224,9 @@ void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n
   // FP32: a gathered side keeps cell records and (ra, dec) apart (the gather
   // then reads from an array half the size); a side read in place keeps them
   // together (one cache line per entry for both)
-  static const bool split_a = std::getenv("HLC_EXP_ACELL") != nullptr;  // experiment switch (temporary)
-  sd.cell32 = (l32 && n_src && (layout || split_a)) ? c.take<CellRec32>(n_src) : nullptr;
-  sd.srcrad = (l32 && n_src && (layout || split_a)) ? c.take<double2>(n_src) : nullptr;
-  sd.src32 = (l32 && n_src && !layout && !split_a) ? c.take<SrcRec32>(n_src) : nullptr;
+  sd.cell32 = (l32 && n_src && layout) ? c.take<CellRec32>(n_src) : nullptr;
+  sd.srcrad = (l32 && n_src && layout) ? c.take<double2>(n_src) : nullptr;
+  sd.src32 = (l32 && n_src && !layout) ? c.take<SrcRec32>(n_src) : nullptr;
 }
 
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {

@@ -123,16 +123,27 @@ void tune_store(const std::string& bucket, const std::vector<double>& values) {
 }
 
 std::string tune_device_tag() {
+  // the properties query is slow: once per device
+  constexpr int MAXDEV = 64;
+  static std::string tags[MAXDEV];
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown|cu0";
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev >= 0 && dev < MAXDEV && !tags[dev].empty()) return tags[dev];
   hipDeviceProp_t p;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
     (void)hipGetLastError();
     return "unknown|cu0";
   }
   std::string arch = p.gcnArchName;
   const size_t colon = arch.find(':');  // drop target features (":sramecc+:xnack-")
   if (colon != std::string::npos) arch.resize(colon);
-  return arch + "|cu" + std::to_string(p.multiProcessorCount);
+  std::string tag = arch + "|cu" + std::to_string(p.multiProcessorCount);
+  if (dev >= 0 && dev < MAXDEV) tags[dev] = tag;
+  return tag;
 }
 
 }  // namespace hlc

@@ -52,7 +52,8 @@ __global__ void k_zero_counters(Counters* c) {
 // ---------------------------------------------------------------------------
 // keygen
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of one value per thread (256 threads).
+// Block-wide exclusive scan of one value per thread (NW waves of 64).
+template <int NW = 4>
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_w) {
   const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
   uint32_t x = v;
@@ -65,7 +66,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uin
   __syncthreads();
   uint32_t wbase = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NW; ++k) {
     uint32_t s = s_w[k];
     if ((uint32_t)k < w) wbase += s;
     tot += s;
@@ -75,11 +76,14 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uin
   return wbase + x - v;
 }
 
-// Each block keys KG_ITEMS * 256 sources; the Dec-halo copies of the block
-// are placed with a single atomic on the halo counter (one per block keeps
-// the contended counter off the critical path).
+// Each block keys KG_ITEMS * KG_THREADS sources, one radix tile (so that it
+// alone counts the tile's first-pass digits); the Dec-halo copies of the
+// block are placed with a single atomic on the halo counter (one per block
+// keeps the contended counter off the critical path).
 constexpr int KG_ITEMS = 16;
-constexpr uint32_t KG_TILE = KG_ITEMS * 256;
+constexpr uint32_t KG_THREADS = 512;
+constexpr uint32_t KG_TILE = KG_ITEMS * KG_THREADS;
+static_assert(KG_TILE == (uint32_t)RS_TILE, "a keygen block fills one radix tile");
 
 __device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
   double sd, cd, sa, ca;
@@ -96,7 +100,7 @@ __device__ inline void unit_vector(double ra, double dec, double& x, double& y, 
 // that certifies candidates. The layout after the sort is then a single
 // gather of one record per entry, from an array a quarter the size of the
 // line traffic of two 8-B gathers of (ra, dec) from the caller's arrays.
-__global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
+__global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
                                                 uint32_t* __restrict__ keys,
@@ -106,16 +110,18 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
                                                 double2* __restrict__ radec32,
                                                 SrcRec32* __restrict__ src32, uint32_t* __restrict__ hist,
                                                 uint32_t hist_tiles, int hist_shift, uint32_t hist_full) {
-  __shared__ uint32_t s_w[4];
+  constexpr int NW = KG_THREADS / 64;
+  __shared__ uint32_t s_w[NW];
   __shared__ unsigned long long s_base;
   __shared__ uint32_t s_h[RS_BINS];
   const uint32_t t = threadIdx.x;
-  // the first radix pass's digit counts of this block's keys, when its radix
-  // tile holds keygen entries only (tiles below hist_full; the others, which
-  // may mix in halo copies, are counted by the pass's own histogram kernel)
-  const uint32_t rtile = (blockIdx.x * KG_TILE) / RS_TILE;
+  // the first radix pass's digit counts of this block's keys (its radix
+  // tile), stored whole when the tile holds keygen entries only (tiles below
+  // hist_full; the others, which may mix in halo copies, are counted by the
+  // pass's own histogram kernel)
+  const uint32_t rtile = blockIdx.x;
   const bool count = hist && rtile < hist_full;
-  if (count) s_h[t] = 0u;
+  if (count && t < (uint32_t)RS_BINS) s_h[t] = 0u;
   __syncthreads();
   const uint32_t base = blockIdx.x * KG_TILE;
   uint32_t hkey[KG_ITEMS];
@@ -126,20 +132,20 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
   if (base + KG_TILE <= n) {
 #pragma unroll
     for (int j = 0; j < KG_ITEMS; ++j) {
-      av[j] = ra[base + (uint32_t)j * 256u + t];
-      dv[j] = dec[base + (uint32_t)j * 256u + t];
+      av[j] = ra[base + (uint32_t)j * KG_THREADS + t];
+      dv[j] = dec[base + (uint32_t)j * KG_THREADS + t];
     }
   } else {
 #pragma unroll
     for (int j = 0; j < KG_ITEMS; ++j) {
-      const uint32_t i = base + (uint32_t)j * 256u + t;
+      const uint32_t i = base + (uint32_t)j * KG_THREADS + t;
       av[j] = i < n ? ra[i] : 0.0;
       dv[j] = i < n ? dec[i] : 0.0;
     }
   }
 #pragma unroll
   for (int j = 0; j < KG_ITEMS; ++j) {
-    const uint32_t i = base + (uint32_t)j * 256u + t;
+    const uint32_t i = base + (uint32_t)j * KG_THREADS + t;
     hkey[j] = 0u;
     if (i < n) {
       double a = av[j], d = dv[j];
@@ -195,11 +201,11 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
   if (bad) atomicOr(&cnt->err, err_bit);
   if (count) {
     __syncthreads();
-    if (s_h[t]) atomicAdd(&hist[(size_t)t * hist_tiles + rtile], s_h[t]);
+    if (t < (uint32_t)RS_BINS) hist[(size_t)t * hist_tiles + rtile] = s_h[t];
   }
   if (!halo) return;
   uint32_t total;
-  const uint32_t off = block_exclusive_scan((uint32_t)__popc(need), &total, s_w);
+  const uint32_t off = block_exclusive_scan<NW>((uint32_t)__popc(need), &total, s_w);
   if (total == 0) return;
   if (t == 0) s_base = atomicAdd(&cnt->n_halo, (unsigned long long)total);
   __syncthreads();
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_keygen(const double* __restrict__ ra,
   for (int j = 0; j < KG_ITEMS; ++j) {
     if (need & (1u << j)) {
       keys[pos] = hkey[j];
-      vals[pos] = (base + (uint32_t)j * 256u + t) | HALO_BIT;
+      vals[pos] = (base + (uint32_t)j * KG_THREADS + t) | HALO_BIT;
       ++pos;
     }
   }
@@ -1090,13 +1096,12 @@ void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& 
     tiles = cdiv(kh->cap, RS_TILE);
     full = n / RS_TILE;
     shift = kh->shift;
+    // (each of those tiles' counts is stored whole by its block: no clearing)
     hist = full ? kh->counts : nullptr;
-    if (hist) k_fill_u32<<<std::min<uint32_t>(cdiv((size_t)RS_BINS * tiles, 256), 4096), 256, 0, s>>>(
-        kh->counts, 0u, (size_t)RS_BINS * tiles);
   }
-  k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), 256, 0, s>>>(ra, dec, n, g, halo ? 1 : 0, err_bit, keys,
-                                                                    vals, cnt, src64, cell32,
-                                                                    radec32, src32, hist, tiles, shift, full);
+  k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), KG_THREADS, 0, s>>>(
+      ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt, src64, cell32, radec32, src32, hist, tiles, shift,
+      full);
 }
 
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s) {

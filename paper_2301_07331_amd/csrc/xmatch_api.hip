@@ -62,13 +62,13 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
       lay(c);
       if (prof) HLC_TRY(hipEventRecord(dev->ev[14], s));
       launch_zero_counters(dev->cnt, s);
-      // A's on the side stream, where A's sort follows, B's beside it on the
-      // caller's stream (the places of B's buffers do not depend on the frame
-      // either)
+      // B's on the caller's stream, launched first (B's chain is the longer
+      // one), A's beside it on the side stream, where A's sort follows (the
+      // places of B's buffers do not depend on the frame either)
       HLC_TRY(hipEventRecord(dev->fork, s));
+      partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
       HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
       partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
-      partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
       spec = true;
     }
   }
@@ -97,16 +97,16 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   // A's partition on the side stream, B's on the caller's, the two keygens
   // side by side; the ranges run on the side stream once both are sorted,
   // beside B's gather (separate sort scratch, disjoint counter fields)
-  if (!self) {
-    if (!keep) {
-      HLC_TRY(hipEventRecord(dev->fork, s));
+  // (B's keygen launched first: B's chain is the longer one)
+  if (!keep) {
+    if (!self) HLC_TRY(hipEventRecord(dev->fork, s));
+    partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
+    if (!self) {
       HLC_TRY(hipStreamWaitEvent(dev->side, dev->fork, 0));
       partition_keys(*dev, a_ra, a_dec, nA, g, false, !fp32, fp32, scA, 1u, A, slA, dev->side);
     }
-  } else {
-    mark(*dev, slA.keygen, s);
   }
-  if (!keep) partition_keys(*dev, b_ra, b_dec, nB, g, true, !fp32, fp32, sc, 2u, B, slB, s);
+  if (self) mark(*dev, slA.keygen, s);
   if (!self) HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, scA, A, slA, dev->side));
   HLC_CHECK(partition_sort(*dev, g, !fp32, fp32, sc, B, slB, s, dev->bsorted));
   if (self) {

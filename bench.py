@@ -41,6 +41,8 @@ MATCH_BYTES = {
 # Whole-call canonical bytes: FP64 (ra, dec) of every source read once and
 # every pair written once.
 CALL_BYTES = lambda na, nb, npairs: 16 * (na + nb) + 16 * npairs
+# VALU issue cycles per second of the whole chip (256 CUs x 4 SIMDs x 2.4 GHz)
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9
 
 # HBM traffic of the filter kernel, measured with rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE passes, scaled by a 1 GiB copy) and recorded
@@ -150,19 +152,23 @@ def pmc_summary(ktrace_dir, pmc_dirs):
         per_wave = lambda n: (mean(c[n]) / waves) if waves and c.get(n) else None
         wait = (mean(c["SQ_WAIT_ANY"]) / mean(c["SQ_WAVE_CYCLES"])
                 if c.get("SQ_WAIT_ANY") and c.get("SQ_WAVE_CYCLES") and mean(c["SQ_WAVE_CYCLES"]) else None)
+        # share of the chip's VALU issue capacity over the kernel's duration:
+        # 4 cycles per wave64 VALU instruction, 1024 SIMDs at 2.4 GHz
+        valu_busy = (4.0 * mean(c["SQ_INSTS_VALU"]) / (t * 1e-6 * VALU_ISSUE_PER_S)
+                     if c.get("SQ_INSTS_VALU") and t else None)
         gbs = ((fb or 0) + (wb or 0)) / (t * 1e-6) / 1e9 if t and (fb is not None or wb is not None) else None
         rows.append((k, t, fb, wb, gbs, waves, per_wave("SQ_INSTS_VALU"), per_wave("SQ_INSTS_VMEM_RD"),
                      per_wave("SQ_INSTS_VMEM_WR"), per_wave("SQ_INSTS_LDS"), mean(c.get("SQ_LDS_BANK_CONFLICT", [])),
-                     wait))
+                     wait, valu_busy))
     fmt = lambda x, p="{:.3g}": "-" if x is None else p.format(x)
     out = ["| kernel | avg us | fetched B | written B | GB/s (fetch+write) | frac of 8 TB/s | waves | VALU/wave "
-           "| VMEM rd/wave | VMEM wr/wave | LDS/wave | LDS bank-conflict cycles | wait/wave-cycles |",
-           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
-    for (k, t, fb, wb, gbs, waves, valu, vr, vw, lds, bc, wait) in rows:
+           "| VMEM rd/wave | VMEM wr/wave | LDS/wave | LDS bank-conflict cycles | wait/wave-cycles | VALU issue share |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (k, t, fb, wb, gbs, waves, valu, vr, vw, lds, bc, wait, vb) in rows:
         out.append(f"| {k} | {fmt(t, '{:.1f}')} | {fmt(fb)} | {fmt(wb)} | {fmt(gbs, '{:.0f}')} | "
                    f"{fmt(gbs / HBM_PEAK_GBS if gbs else None, '{:.3f}')} | {fmt(waves, '{:.0f}')} | {fmt(valu, '{:.0f}')} | "
                    f"{fmt(vr, '{:.1f}')} | {fmt(vw, '{:.1f}')} | {fmt(lds, '{:.1f}')} | {fmt(bc, '{:.3g}')} | "
-                   f"{fmt(wait, '{:.2f}')} |")
+                   f"{fmt(wait, '{:.2f}')} | {fmt(vb, '{:.2f}')} |")
     out.append("")
     out.append(f"copy scaling: " + ", ".join(f"{c} x{v:.4f}" for c, v in scale.items()))
     return "\n".join(out)

@@ -69,9 +69,11 @@ void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,
                         hipStream_t s);
 // the same read from the key index (requires rb + fb >= shift: every zone's
-// first key is then a multiple of the index step)
+// first key is then a multiple of the index step); with zmarg, also the zone
+// tables of launch_zone_tables
 void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const DevCount& n, const Geom& g,
-                              uint32_t* zstart, hipStream_t s);
+                              uint32_t* zstart, hipStream_t s, int32_t* zmarg = nullptr,
+                              double* zdelta = nullptr);
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s);
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,

@@ -368,37 +368,39 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 // Per zone: the RA half-width (deg, padded outward) of a window of radius
 // r around any of its sources, and that width in bins plus one (-1 for
 // both: the zone is scanned as a whole ring)
-__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double* __restrict__ zdelta) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (uint32_t)g.nz) {
-    const int32_t z = (int32_t)i;
-    double lo = zone_lo(g, z);
-    double hi = lo + zone_height(g, z);
-    // largest |Dec| a source assigned to this zone can have (padded for the
-    // rounding of the zone formula)
-    double dstar = fmin(fmax(fabs(lo), fabs(hi)) + 1e-9, 90.0);
-    int32_t m = -1;  // -1: whole zone ring
-    double dz = -1.0;
-    if (dstar + g.rpad_deg < 90.0) {
-      double ss, cs, sd, cd;
-      sincos_deg(g.rpad_deg, &ss, &cs);
-      sincos_deg(dstar, &sd, &cd);
-      double x = ss / cd;
-      if (x < 0.99) {
-        double delta = asin(x) * (180.0 / M_PI) * (1.0 + 1e-9) + 1e-12;
-        // floor(ra * scale) is monotone in ra, and a shift by delta moves it
-        // by at most ceil(delta * scale) + 1 bins (one for the rounding of
-        // the product)
-        double mm = ceil(delta * g.bin_scale) + 1.0;
-        if (2.0 * mm + 1.0 < (double)g.nbins) {
-          m = (int32_t)mm;
-          dz = delta;
-        }
+__device__ inline void zone_table_entry(const Geom& g, int32_t z, int32_t* __restrict__ zmarg,
+                                        double* __restrict__ zdelta) {
+  double lo = zone_lo(g, z);
+  double hi = lo + zone_height(g, z);
+  // largest |Dec| a source assigned to this zone can have (padded for the
+  // rounding of the zone formula)
+  double dstar = fmin(fmax(fabs(lo), fabs(hi)) + 1e-9, 90.0);
+  int32_t m = -1;  // -1: whole zone ring
+  double dz = -1.0;
+  if (dstar + g.rpad_deg < 90.0) {
+    double ss, cs, sd, cd;
+    sincos_deg(g.rpad_deg, &ss, &cs);
+    sincos_deg(dstar, &sd, &cd);
+    double x = ss / cd;
+    if (x < 0.99) {
+      double delta = asin(x) * (180.0 / M_PI) * (1.0 + 1e-9) + 1e-12;
+      // floor(ra * scale) is monotone in ra, and a shift by delta moves it
+      // by at most ceil(delta * scale) + 1 bins (one for the rounding of
+      // the product)
+      double mm = ceil(delta * g.bin_scale) + 1.0;
+      if (2.0 * mm + 1.0 < (double)g.nbins) {
+        m = (int32_t)mm;
+        dz = delta;
       }
     }
-    zmarg[z] = m;
-    zdelta[z] = dz;
   }
+  zmarg[z] = m;
+  zdelta[z] = dz;
+}
+
+__global__ void k_zone_tables(Geom g, int32_t* __restrict__ zmarg, double* __restrict__ zdelta) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (uint32_t)g.nz) zone_table_entry(g, (int32_t)i, zmarg, zdelta);
 }
 
 __device__ inline uint32_t lower_bound_u32(const uint32_t* keys, uint32_t lo, uint32_t hi, uint32_t K) {
@@ -421,12 +423,15 @@ __global__ void k_zone_starts(const uint32_t* __restrict__ keys, DevCount nc, Ge
 
 // The same from the coarse key index when a zone's first key is a multiple
 // of the index's step (idx[i] = first position with key >= i << shift).
+// With zmarg, the zone tables as well (one launch for both).
 __global__ void k_zone_starts_index(const uint32_t* __restrict__ idx, int shift, uint32_t T, DevCount nc, Geom g,
-                                    uint32_t* __restrict__ zstart) {
+                                    uint32_t* __restrict__ zstart, int32_t* __restrict__ zmarg,
+                                    double* __restrict__ zdelta) {
   const uint32_t n = nc.get();
   uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z > (uint32_t)g.nz) return;
   if (z == (uint32_t)g.nz) { zstart[z] = n; return; }
+  if (zmarg) zone_table_entry(g, (int32_t)z, zmarg, zdelta);
   const uint32_t i = make_key(g, (int32_t)z, 0u) >> shift;
   zstart[z] = i < T ? idx[i] : n;
 }
@@ -1178,8 +1183,8 @@ void launch_zone_tables(const Geom& g, int32_t* zmarg, double* zdelta, hipStream
 }
 
 void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const DevCount& n, const Geom& g,
-                              uint32_t* zstart, hipStream_t s) {
-  k_zone_starts_index<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(idx, shift, T, n, g, zstart);
+                              uint32_t* zstart, hipStream_t s, int32_t* zmarg, double* zdelta) {
+  k_zone_starts_index<<<cdiv((uint32_t)g.nz + 1, 256), 256, 0, s>>>(idx, shift, T, n, g, zstart, zmarg, zdelta);
 }
 
 void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, uint32_t* zstart,

@@ -130,16 +130,19 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   // (ordered by the caller after both sorts) they overlap B's gather on s
   if (!ps) ps = s;
   Thresholds th = thresholds(r_arcsec);
-  launch_zone_tables(g, w.zmarg, w.zdelta, ps);
   const KeyIndex ki = key_index_dims(g);
   launch_key_index(B.keys, B.cnt, ki.shift, ki.T, w.kidx, ps);
   const uint32_t* zstart = w.zstartB;
-  if (!zstart) {
-    // from the index when zone boundaries fall on its entries, else searched
-    if (g.rb + g.fb >= ki.shift) launch_zone_starts_index(w.kidx, ki.shift, ki.T, B.cnt, g, w.zstart_buf, ps);
-    else launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, ps);
-    zstart = w.zstart_buf;
+  // zone starts from the index when zone boundaries fall on its entries (with
+  // the zone tables in the same launch), else searched
+  const bool from_index = !zstart && g.rb + g.fb >= ki.shift;
+  if (from_index) {
+    launch_zone_starts_index(w.kidx, ki.shift, ki.T, B.cnt, g, w.zstart_buf, ps, w.zmarg, w.zdelta);
+  } else {
+    launch_zone_tables(g, w.zmarg, w.zdelta, ps);
+    if (!zstart) launch_zone_starts(B.keys, B.cnt, g, w.zstart_buf, ps);
   }
+  if (!zstart) zstart = w.zstart_buf;
   launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, ps);
   if (prof >= PROF_ALL) (void)hipEventRecord(dev.ev[8], ps);
   // the candidate regions are cleared before the join, beside the ranges

@@ -16,6 +16,8 @@
 //     per-tile histograms, a device-wide scan, LDS-staged stable scatter).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "hlc_kernels.hpp"
 
 namespace hlc {
@@ -272,6 +274,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_scan_digits(uint32_t* __restrict
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// One stable scatter pass over 8,192-key tiles, persistent: block b takes
+// tiles b, b + G, ... of the entries present (G blocks), and the next tile's
+// keys and values are loaded while the current one is ranked and written, so
+// that a block's loads do not wait behind its own ranking. A tile is ranked
+// in LDS (per-wave digit counts, 8 ballots per item for the lanes sharing a
+// digit) and leaves in runs of consecutive positions.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, DevCount nc, int shift,
@@ -281,84 +289,102 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   __shared__ uint32_t s_wh[4][RS_BINS];
   __shared__ uint32_t s_start[RS_BINS];
   __shared__ uint32_t s_goff[RS_BINS];
+  __shared__ uint32_t s_dbase[RS_BINS];
   __shared__ uint32_t s_w[4];
   const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const uint32_t tile = blockIdx.x;
-  const uint32_t base = tile * RS_TILE;
   const uint32_t n = nc.get();
-  if (base >= n) return;  // tile beyond the device-side count (block-uniform)
-  const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
-
-  for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
+  const uint32_t nt = (uint32_t)(((uint64_t)n + RS_TILE - 1) / RS_TILE);
+  uint32_t tile = blockIdx.x;
+  if (tile >= nt) return;  // (block-uniform)
   {
+    // digit d's first position before any tile's share: the same for every tile
     uint32_t all;
-    const uint32_t digit_base = block_exclusive_scan(totals[t], &all, s_w);
-    s_goff[t] = digit_base + offsets[t * ntiles + tile];
+    s_dbase[t] = block_exclusive_scan(totals[t], &all, s_w);
   }
-  __syncthreads();
-
-  // wave w owns tile elements [w*1024, (w+1)*1024), 64 per round; every
-  // load in flight before the first use
-  uint32_t key[RS_ITEMS], val[RS_ITEMS];
-  const uint32_t e0 = base + w * (RS_TILE / 4) + lane;
-  if (tile_n == (uint32_t)RS_TILE) {
+  auto load = [&](uint32_t tl, uint32_t (&k)[RS_ITEMS], uint32_t (&v)[RS_ITEMS], uint32_t& off) {
+    const uint32_t e0 = tl * RS_TILE + w * (RS_TILE / 4) + lane;
+    off = offsets[t * ntiles + tl];
+    if (tl * RS_TILE + RS_TILE <= n) {
 #pragma unroll
-    for (int j = 0; j < RS_ITEMS; ++j) {
-      key[j] = keys_in[e0 + j * 64];
-      val[j] = vals_in[e0 + j * 64];
+      for (int j = 0; j < RS_ITEMS; ++j) {
+        k[j] = keys_in[e0 + j * 64];
+        v[j] = vals_in[e0 + j * 64];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < RS_ITEMS; ++j) {
+        const uint32_t e = e0 + j * 64;
+        k[j] = e < n ? keys_in[e] : 0u;
+        v[j] = e < n ? vals_in[e] : 0u;
+      }
     }
-  } else {
+  };
+  uint32_t key[RS_ITEMS], val[RS_ITEMS], off;
+  load(tile, key, val, off);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  while (true) {
+    const uint32_t base = tile * RS_TILE;
+    const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
+    const uint32_t next = tile + gridDim.x;
+    for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
+    s_goff[t] = s_dbase[t] + off;
+    __syncthreads();
+    const uint32_t e0 = base + w * (RS_TILE / 4) + lane;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j)
+      if (e0 + j * 64 < n) atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    {
+      const uint32_t d = t;
+      uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
+      uint32_t tot;
+      uint32_t st = block_exclusive_scan(c0 + c1 + c2 + c3, &tot, s_w);
+      s_start[d] = st;
+      s_wh[0][d] = st;
+      s_wh[1][d] = st + c0;
+      s_wh[2][d] = st + c0 + c1;
+      s_wh[3][d] = st + c0 + c1 + c2;
+    }
+    __syncthreads();
+    // the next tile in flight from here on
+    uint32_t nkey[RS_ITEMS], nval[RS_ITEMS], noff = 0u;
+    if (next < nt) load(next, nkey, nval, noff);
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
       const uint32_t e = e0 + j * 64;
-      key[j] = e < n ? keys_in[e] : 0u;
-      val[j] = e < n ? vals_in[e] : 0u;
-    }
-  }
+      const bool valid = e < n;
+      const uint32_t d = (key[j] >> shift) & 0xffu;
+      uint64_t peers = __ballot(valid);
 #pragma unroll
-  for (int j = 0; j < RS_ITEMS; ++j)
-    if (e0 + j * 64 < n) atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
-  __syncthreads();
-  {
-    const uint32_t d = t;
-    uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
-    uint32_t tot;
-    uint32_t st = block_exclusive_scan(c0 + c1 + c2 + c3, &tot, s_w);
-    s_start[d] = st;
-    s_wh[0][d] = st;
-    s_wh[1][d] = st + c0;
-    s_wh[2][d] = st + c0 + c1;
-    s_wh[3][d] = st + c0 + c1 + c2;
-  }
-  __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-  for (int j = 0; j < RS_ITEMS; ++j) {
-    uint32_t e = base + w * (RS_TILE / 4) + j * 64 + lane;
-    bool valid = e < n;
-    uint32_t d = (key[j] >> shift) & 0xffu;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      uint64_t b = __ballot((d >> bit) & 1u);
-      peers &= ((d >> bit) & 1u) ? b : ~b;
+      for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t b = __ballot((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? b : ~b;
+      }
+      if (valid) {
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const uint32_t pos = s_wh[w][d] + rank;
+        s_k[pos] = key[j];
+        s_v[pos] = val[j];
+        if ((peers >> lane) == 1ull) s_wh[w][d] += rank + 1u;
+      }
     }
-    if (valid) {
-      uint32_t rank = (uint32_t)__popcll(peers & lt);
-      uint32_t pos = s_wh[w][d] + rank;
-      s_k[pos] = key[j];
-      s_v[pos] = val[j];
-      // the highest lane of each digit group advances that digit's cursor
-      if ((peers >> lane) == 1ull) s_wh[w][d] += rank + 1u;
+    __syncthreads();
+    for (uint32_t i = t; i < tile_n; i += RS_THREADS) {
+      const uint32_t k = s_k[i];
+      const uint32_t d = (k >> shift) & 0xffu;
+      const uint32_t gpos = s_goff[d] + (i - s_start[d]);
+      keys_out[gpos] = k;
+      vals_out[gpos] = s_v[i];
     }
-  }
-  __syncthreads();
-  for (uint32_t i = t; i < tile_n; i += RS_THREADS) {
-    uint32_t k = s_k[i];
-    uint32_t d = (k >> shift) & 0xffu;
-    uint32_t gpos = s_goff[d] + (i - s_start[d]);
-    keys_out[gpos] = k;
-    vals_out[gpos] = s_v[i];
+    if (next >= nt) break;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+      key[j] = nkey[j];
+      val[j] = nval[j];
+    }
+    off = noff;
+    tile = next;
+    __syncthreads();  // the tile's LDS is read out before the next one fills it
   }
 }
 
@@ -1127,6 +1153,20 @@ int radix_passes(int key_bits, int lo_bit) { return (key_bits - lo_bit + 7) / 8;
 
 uint32_t keygen_hist_tiles(uint32_t n) { return n / RS_TILE; }
 
+// blocks of the persistent scatter: two per CU (as many as its LDS allows)
+static uint32_t scatter_blocks() {
+  static const uint32_t v = [] {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+      (void)hipGetLastError();
+      cus = 256;
+    }
+    return 2u * (uint32_t)cus;
+  }();
+  return v;
+}
+
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
                 hipStream_t s, bool from_alt, int lo_bit, uint32_t hist_done) {
   const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
@@ -1144,8 +1184,8 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bit
       const uint32_t h0 = p == 0 ? std::min(hist_done, ntiles) : 0u;
       if (h0 < ntiles) k_radix_hist<<<ntiles - h0, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles, h0);
       k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
-      k_radix_scatter<<<ntiles, RS_THREADS, 0, s>>>(kin, vin, kout, vout, cnt, shift, sc.counts,
-                                                    sc.digit_totals, ntiles);
+      k_radix_scatter<<<std::min<uint32_t>(ntiles, scatter_blocks()), RS_THREADS, 0, s>>>(
+          kin, vin, kout, vout, cnt, shift, sc.counts, sc.digit_totals, ntiles);
       std::swap(kin, kout);
       std::swap(vin, vout);
     }

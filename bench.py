@@ -121,10 +121,13 @@ def pmc_summary(ktrace_dir, pmc_dirs):
     wait and LDS-conflict figures where the passes hold them. Markdown."""
     import csv
     from collections import defaultdict
-    dur = {}
+    dur, calls = {}, {}
     for f in _csvs(ktrace_dir, "kernel_stats.csv"):
         for r in csv.DictReader(open(f)):
+            if "hlc" not in r["Name"]:
+                continue
             dur[short_kernel(r["Name"])] = float(r["AverageNs"]) * 1e-3
+            calls[short_kernel(r["Name"])] = int(r["Calls"])
     vals = defaultdict(lambda: defaultdict(list))  # kernel -> counter -> per-dispatch values
     copy = defaultdict(list)
     for d in pmc_dirs:
@@ -141,7 +144,7 @@ def pmc_summary(ktrace_dir, pmc_dirs):
     scale = {c: gib_kib / max(copy[c]) for c in ("FETCH_SIZE", "WRITE_SIZE") if copy.get(c)}
     mean = lambda x: sum(x) / len(x) if x else None
     rows = []
-    for k in sorted(vals, key=lambda k: -(dur.get(k) or 0)):
+    for k in sorted(set(vals) | set(dur), key=lambda k: -(dur.get(k) or 0)):
         c = vals[k]
         f = mean(c.get("FETCH_SIZE", []))
         w = mean(c.get("WRITE_SIZE", []))
@@ -157,15 +160,15 @@ def pmc_summary(ktrace_dir, pmc_dirs):
         valu_busy = (4.0 * mean(c["SQ_INSTS_VALU"]) / (t * 1e-6 * VALU_ISSUE_PER_S)
                      if c.get("SQ_INSTS_VALU") and t else None)
         gbs = ((fb or 0) + (wb or 0)) / (t * 1e-6) / 1e9 if t and (fb is not None or wb is not None) else None
-        rows.append((k, t, fb, wb, gbs, waves, per_wave("SQ_INSTS_VALU"), per_wave("SQ_INSTS_VMEM_RD"),
+        rows.append((k, calls.get(k), t, fb, wb, gbs, waves, per_wave("SQ_INSTS_VALU"), per_wave("SQ_INSTS_VMEM_RD"),
                      per_wave("SQ_INSTS_VMEM_WR"), per_wave("SQ_INSTS_LDS"), mean(c.get("SQ_LDS_BANK_CONFLICT", [])),
                      wait, valu_busy))
     fmt = lambda x, p="{:.3g}": "-" if x is None else p.format(x)
-    out = ["| kernel | avg us | fetched B | written B | GB/s (fetch+write) | frac of 8 TB/s | waves | VALU/wave "
+    out = ["| kernel | calls | avg us | fetched B | written B | GB/s (fetch+write) | frac of 8 TB/s | waves | VALU/wave "
            "| VMEM rd/wave | VMEM wr/wave | LDS/wave | LDS bank-conflict cycles | wait/wave-cycles | VALU issue share |",
-           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
-    for (k, t, fb, wb, gbs, waves, valu, vr, vw, lds, bc, wait, vb) in rows:
-        out.append(f"| {k} | {fmt(t, '{:.1f}')} | {fmt(fb)} | {fmt(wb)} | {fmt(gbs, '{:.0f}')} | "
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (k, nc, t, fb, wb, gbs, waves, valu, vr, vw, lds, bc, wait, vb) in rows:
+        out.append(f"| {k} | {fmt(nc, '{:d}')} | {fmt(t, '{:.1f}')} | {fmt(fb)} | {fmt(wb)} | {fmt(gbs, '{:.0f}')} | "
                    f"{fmt(gbs / HBM_PEAK_GBS if gbs else None, '{:.3f}')} | {fmt(waves, '{:.0f}')} | {fmt(valu, '{:.0f}')} | "
                    f"{fmt(vr, '{:.1f}')} | {fmt(vw, '{:.1f}')} | {fmt(lds, '{:.1f}')} | {fmt(bc, '{:.3g}')} | "
                    f"{fmt(wait, '{:.2f}')} | {fmt(vb, '{:.2f}')} |")

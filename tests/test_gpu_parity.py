@@ -572,3 +572,31 @@ def test_polar_band_edges(hlc, prec):
             keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec, tuning=tun)
             assert_same(keys, sep, ref, label=f"polar band edges r={r} tuning={tun}")
         _print("polar band edges r", r, "pairs", len(ref), hlc.last_stats())
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_sparse_key_space(hlc, prec):
+    """A whole-sphere frame that is almost empty: three dense clumps far
+    apart and a few isolated sources at the extremes of Dec and RA. Most of
+    the coarse key index then lies in long empty runs (the stretches one wave
+    writes together) and most radix digits are empty."""
+    g = synth.rng(910, 0)
+    ARC = 1.0 / 3600.0
+    for r in (1.0, 20.0):
+        parts_a, parts_b = [], []
+        for (ra0, dec0) in ((10.0, 60.0), (200.0, -30.0), (359.99, 0.0)):
+            ra, dec = synth.cone(g, 4000, ra0, dec0, 200 * r * ARC)
+            parts_a.append((ra, dec))
+            parts_b.append(synth.gaussian_offset(g, ra[:2500], dec[:2500], 0.5 * r * ARC))
+        iso = (np.array([0.0, 90.0, 180.0, 270.0, 359.999999]), np.array([-89.99, -45.0, 0.0, 45.0, 89.99]))
+        parts_a.append(iso)
+        parts_b.append(iso)
+        a_ra = synth._wrap_ra(np.concatenate([p[0] for p in parts_a]))
+        a_dec = np.concatenate([p[1] for p in parts_a])
+        b_ra = synth._wrap_ra(np.concatenate([p[0] for p in parts_b]))
+        b_dec = np.concatenate([p[1] for p in parts_b])
+        ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+        assert len(ref) > 1000, r
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, prec)
+        assert_same(keys, sep, ref, label=f"sparse key space r={r}")
+        _print("sparse key space r", r, "pairs", len(ref), hlc.last_stats())

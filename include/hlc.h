@@ -53,12 +53,16 @@ typedef enum {
   HLC_E_NOMEM = -2,       /* device or host allocation failed                     */
   HLC_E_OVERFLOW = -3,    /* more pairs than opts->capacity; *n_pairs = required  */
   HLC_E_DEVICE = -4,      /* HIP runtime error                                    */
-  HLC_E_UNSUPPORTED = -5  /* valid request this build does not handle             */
+  HLC_E_UNSUPPORTED = -5  /* valid request the library does not handle            */
 } hlc_status;
 
 /* Filter precision. Both give the same exact pair set; they differ in speed.
- *   HLC_FP32_RECHECK: candidate filter in FP32 on offsets from per-cell
- *     centres, every candidate certified in FP64 (default).
+ *   HLC_FP32_RECHECK: candidate filter in FP32 on offsets from a centre per
+ *     group of 16 A sources (each unit vector stored as its FP32 lattice
+ *     corner plus a fixed-point offset of 2^-34 per axis), against a bound
+ *     that covers every FP32 rounding; every candidate is then certified in
+ *     FP64 (default). The batched form's FP32 filter works on offsets from
+ *     each job's frame centre.
  *   HLC_FP64: candidate filter in FP64 on unit vectors.                     */
 typedef enum { HLC_FP32_RECHECK = 0, HLC_FP64 = 1 } hlc_precision;
 

@@ -200,7 +200,6 @@ struct MatchArgs {
   int a_in_place;
   const Rec64* srcA64;
   const SrcRec32* srcA32;
-  const CellRec32* cellA;       // (experiment) A's cell records in place, apart from (ra, dec)
   const uint32_t* keysA;
   const uint32_t* keysB;
   Geom geom;

@@ -410,10 +410,7 @@ __device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
   r.key = a.keysA[h.a_pos];
   const uint32_t idx = h.va;  // the entry's source index (halo bit included)
   if constexpr (F32) {
-    if (a.a_in_place && a.cellA) {
-      r.ca = a.cellA[idx & IDX_MASK];
-      r.u0 = __builtin_nan("");
-    } else if (a.a_in_place) {
+    if (a.a_in_place) {
       const SrcRec32 s = a.srcA32[idx & IDX_MASK];
       r.ca = s.c;
       r.u0 = s.ra;

@@ -178,7 +178,6 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
     ma.a_in_place = 1;
     ma.srcA64 = A.src64;
     ma.srcA32 = A.src32;
-    ma.cellA = A.src32 ? nullptr : A.cell32;
   }
   ma.geom = g;
   ma.H_lo = th.H_lo;

@@ -20,7 +20,8 @@ struct SortScratch {
 
 // keys/vals for A (one entry per source, or one per source plus Dec-halo
 // copies appended after n when `halo` is set).
-// keys (and halo copies) of n sources; with src64 (FP64 form), cell32 and
+// keys (and halo copies) of n sources (with iota_vals, the value of source i,
+// i itself, is left to the sort's first pass); with src64 (FP64 form), cell32 and
 // radec32 (FP32 form, a catalogue whose records are gathered) or src32 (FP32
 // form, a catalogue the filter reads in place) also each source's working
 // record in input order, for launch_gather64 / 32, the filter and the
@@ -36,7 +37,7 @@ struct KeygenHist {
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
                    Rec64* src64 = nullptr, CellRec32* cell32 = nullptr, double2* radec32 = nullptr,
-                   SrcRec32* src32 = nullptr, const KeygenHist* kh = nullptr);
+                   SrcRec32* src32 = nullptr, const KeygenHist* kh = nullptr, bool iota_vals = false);
 // tiles of the first pass whose counts a keygen of n sources fills
 uint32_t keygen_hist_tiles(uint32_t n);
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s);
@@ -54,9 +55,13 @@ int radix_passes(int key_bits, int lo_bit = 0);
 // vals, tmp_pairs, tmp_sep hold n entries each
 void sort_pairs(uint2* pairs, double* sep, uint32_t n, int bits_a, int bits_b, uint32_t* keys, uint32_t* vals,
                 uint2* tmp_pairs, double* tmp_sep, const SortScratch& sc, hipStream_t s);
-// hist_done: tiles whose first-pass counts are already in sc.counts (keygen)
+// hist_done: tiles whose first-pass counts are already in sc.counts (keygen);
+// iota: entries below it take their position as value in the first pass
+// (their values are not read: with iota_vals the keygen does not write them;
+// at least one pass must run)
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& n, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt = false, int lo_bit = 0, uint32_t hist_done = 0);
+                hipStream_t s, bool from_alt = false, int lo_bit = 0, uint32_t hist_done = 0,
+                uint32_t iota = 0);
 
 // footprint of the valid sources into Counters::ext (max-combined): a
 // sample of at most 2 x 4096 sources (overwrites; also written to msg[0..3]

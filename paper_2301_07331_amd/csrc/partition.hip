@@ -111,7 +111,8 @@ __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict_
                                                 CellRec32* __restrict__ cell32,
                                                 double2* __restrict__ radec32,
                                                 SrcRec32* __restrict__ src32, uint32_t* __restrict__ hist,
-                                                uint32_t hist_tiles, int hist_shift, uint32_t hist_full) {
+                                                uint32_t hist_tiles, int hist_shift, uint32_t hist_full,
+                                                int iota_vals) {
   constexpr int NW = KG_THREADS / 64;
   __shared__ uint32_t s_w[NW];
   __shared__ unsigned long long s_base;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict_
       const uint32_t fr = frac_of(g, a, b);
       const uint32_t key = make_key(g, z, b) | fr;
       keys[i] = key;
-      vals[i] = i;
+      if (!iota_vals) vals[i] = i;  // (else the sort's first pass takes the position)
       if (count) atomicAdd(&s_h[(key >> hist_shift) & 0xffu], 1u);
       if (src64 || cell32 || src32) {
         double x, y, w;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_scan_digits(uint32_t* __restrict
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, DevCount nc, int shift,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ totals, uint32_t ntiles) {
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ totals, uint32_t ntiles, uint32_t iota) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[RS_TILE];
   __shared__ uint32_t s_wh[4][RS_BINS];
@@ -304,18 +305,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   auto load = [&](uint32_t tl, uint32_t (&k)[RS_ITEMS], uint32_t (&v)[RS_ITEMS], uint32_t& off) {
     const uint32_t e0 = tl * RS_TILE + w * (RS_TILE / 4) + lane;
     off = offsets[t * ntiles + tl];
-    if (tl * RS_TILE + RS_TILE <= n) {
+    // (entries below iota carry their own position as value: not loaded)
+    if (tl * RS_TILE + RS_TILE <= min(n, iota)) {
 #pragma unroll
       for (int j = 0; j < RS_ITEMS; ++j) {
         k[j] = keys_in[e0 + j * 64];
-        v[j] = vals_in[e0 + j * 64];
+        v[j] = e0 + j * 64;
+      }
+    } else if (tl * RS_TILE + RS_TILE <= n) {
+#pragma unroll
+      for (int j = 0; j < RS_ITEMS; ++j) {
+        const uint32_t e = e0 + j * 64;
+        k[j] = keys_in[e];
+        v[j] = e < iota ? e : vals_in[e];
       }
     } else {
 #pragma unroll
       for (int j = 0; j < RS_ITEMS; ++j) {
         const uint32_t e = e0 + j * 64;
         k[j] = e < n ? keys_in[e] : 0u;
-        v[j] = e < n ? vals_in[e] : 0u;
+        v[j] = e < n ? (e < iota ? e : vals_in[e]) : 0u;
       }
     }
   };
@@ -1118,7 +1127,8 @@ void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64,
 
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
-                   Rec64* src64, CellRec32* cell32, double2* radec32, SrcRec32* src32, const KeygenHist* kh) {
+                   Rec64* src64, CellRec32* cell32, double2* radec32, SrcRec32* src32, const KeygenHist* kh,
+                   bool iota_vals) {
   if (n == 0) return;
   uint32_t* hist = nullptr;
   uint32_t tiles = 0, full = 0;
@@ -1132,7 +1142,7 @@ void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& 
   }
   k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), KG_THREADS, 0, s>>>(
       ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt, src64, cell32, radec32, src32, hist, tiles, shift,
-      full);
+      full, iota_vals ? 1 : 0);
 }
 
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s) {
@@ -1168,7 +1178,7 @@ static uint32_t scatter_blocks() {
 }
 
 void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bits, const SortScratch& sc,
-                hipStream_t s, bool from_alt, int lo_bit, uint32_t hist_done) {
+                hipStream_t s, bool from_alt, int lo_bit, uint32_t hist_done, uint32_t iota) {
   const uint32_t n = cnt.cap;  // grids cover the capacity; kernels read the count
   const int passes = radix_passes(key_bits, lo_bit);
   uint32_t *kin = keys, *vin = vals, *kout = sc.keys_alt, *vout = sc.vals_alt;
@@ -1185,7 +1195,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bit
       if (h0 < ntiles) k_radix_hist<<<ntiles - h0, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles, h0);
       k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
       k_radix_scatter<<<std::min<uint32_t>(ntiles, scatter_blocks()), RS_THREADS, 0, s>>>(
-          kin, vin, kout, vout, cnt, shift, sc.counts, sc.digit_totals, ntiles);
+          kin, vin, kout, vout, cnt, shift, sc.counts, sc.digit_totals, ntiles, p == 0 ? iota : 0u);
       std::swap(kin, kout);
       std::swap(vin, vout);
     }

@@ -11,6 +11,12 @@
 
 namespace hlc {
 
+// Source i's value is i: the keygen leaves it to the sort's first pass when
+// a pass runs (the entries' capacity above one, sorted key bits present).
+static bool iota_values(const Geom& g, const Side& sd) {
+  return sd.n_cap > 1 && radix_passes(key_bits(g), sort_lo(g)) > 0;
+}
+
 void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                     bool l64, bool l32, const SortScratch& sc, uint32_t err_bit, Side& sd, const Slots& sl,
                     hipStream_t s) {
@@ -25,7 +31,8 @@ void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n
   // the keygen also counts the first radix pass's digits of the tiles it alone fills
   const KeygenHist kh{sc.counts, sd.n_cap, sort_lo(g)};
   launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
-                l32 ? sd.cell32 : nullptr, l32 ? sd.srcrad : nullptr, l32 ? sd.src32 : nullptr, &kh);
+                l32 ? sd.cell32 : nullptr, l32 ? sd.srcrad : nullptr, l32 ? sd.src32 : nullptr, &kh,
+                iota_values(g, sd));
   mark(dev, sl.keygen, s);
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
 }
@@ -35,7 +42,8 @@ int partition_sort(Device& dev, const Geom& g, bool l64, bool l32, const SortScr
   const int bits = key_bits(g);
   const bool from_alt = (radix_passes(bits, sort_lo(g)) & 1) != 0;
   mark(dev, sl.sort_begin, s);
-  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, sort_lo(g), keygen_hist_tiles(sd.n_src));
+  radix_sort(sd.keys, sd.vals, sd.cnt, bits, sc, s, from_alt, sort_lo(g), keygen_hist_tiles(sd.n_src),
+             iota_values(g, sd) ? sd.n_src : 0u);
   mark(dev, sl.sort, s);
   if (sorted_ev) HLC_TRY(hipEventRecord(sorted_ev, s));
   if (l64 && sd.r64) {

@@ -404,7 +404,7 @@ int batch_impl(const hlc_job* jobs, int32_t njobs, const double* a_ra, const dou
 
   unsigned long long* jcount = reinterpret_cast<unsigned long long*>(job_pair_count);
   const uint64_t cap = (uint64_t)o->capacity;
-  Caps caps = initial_caps(*dev, (uint64_t)(P0.NA + P0.NB), cap, false);
+  Caps caps = initial_caps(*dev, (uint64_t)(P0.NA + P0.NB), cap, false, true);
   double* sep = (o->flags & HLC_NO_SEP) ? nullptr : out_sep;
 
   for (int attempt = 0; attempt < 3; ++attempt) {

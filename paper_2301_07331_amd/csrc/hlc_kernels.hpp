@@ -98,10 +98,13 @@ void launch_ranges(const uint32_t* keysA, const DevCount& na, const uint32_t* ki
 
 // ---- match.hip -------------------------------------------------------------
 // Output allocation. A single counter bumped by every wave serialises at the
-// memory side (device-scope atomics on one address), so pairs are appended
-// to NREG striped staging regions instead (region = wave index mod NREG,
-// counters 256 B apart) and a compaction kernel packs the regions into the
-// caller's buffer in region order. Filter candidates are staged the same way.
+// memory side (device-scope atomics on one address: a few ns each), so the
+// filter appends its candidates to NREG striped staging regions (region =
+// wave index mod NREG, counters 256 B apart). The certification of a single
+// call writes its pairs straight into the caller's buffer, one atomic on the
+// pair count per block and round of 1,024 candidates (OutArgs::direct); the
+// batched form and the paper-scheme emulation stage pairs in regions too, and
+// a compaction kernel packs them into the caller's buffer in region order.
 constexpr int NREG = 256;
 constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
 
@@ -121,7 +124,7 @@ struct Cand {
 struct Regions {
   unsigned long long* fill;     // NREG * REG_STRIDE; fill[k * REG_STRIDE] = pairs sent to region k
   unsigned long long* cfill;    // NREG * REG_STRIDE; candidates sent to region k
-  uint2* pairs;                 // NREG * S staging
+  uint2* pairs;                 // NREG * S staging (nullptr when S = 0: pairs written directly)
   double* sep;                  // NREG * S staging, or nullptr
   unsigned long long S;         // pair slots per region
   Cand* cand;                   // NREG * Sc staged candidates, or nullptr
@@ -138,6 +141,7 @@ struct OutArgs {
   unsigned long long band_cap;
   Counters* cnt;
   Regions reg;
+  int direct;  // certified pairs straight into pairs/sep (block-aggregated counter), not through regions
 };
 
 __device__ inline uint32_t wave_region() {
@@ -166,6 +170,14 @@ __device__ inline void emit_wave(bool in, uint32_t ia, uint32_t ib, double sep, 
 
 // One pair from one thread (rare paths: band certification).
 __device__ inline void emit_one(uint32_t ia, uint32_t ib, double sep, const OutArgs& o) {
+  if (o.direct) {
+    const unsigned long long slot = atomicAdd(&o.cnt->n_pairs, 1ull);
+    if (slot < o.cap) {
+      o.pairs[slot] = make_uint2(ia, ib);
+      if (o.sep) o.sep[slot] = sep;
+    }
+    return;
+  }
   const uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) & (NREG - 1);
   const unsigned long long slot = atomicAdd(&o.reg.fill[k * REG_STRIDE], 1ull);
   if (slot < o.reg.S) {

@@ -296,7 +296,9 @@ struct Caps {
   uint64_t cand;
 };
 
-Caps initial_caps(const Device& d, uint64_t entries, uint64_t cap, bool stage_cand);
+// pair_regions: pairs staged in regions and compacted (else written straight
+// into the caller's buffer by the certification: no pair slots)
+Caps initial_caps(const Device& d, uint64_t entries, uint64_t cap, bool stage_cand, bool pair_regions);
 void carve_regions(Carve& c, Regions& r, const Caps& k, bool sep);
 // True when the call must run again: its band list overflowed, a candidate
 // region overflowed, or a pair region overflowed although the caller's

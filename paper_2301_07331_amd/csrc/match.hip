@@ -166,11 +166,31 @@ __device__ inline Verdict certify32(const MatchArgs& a, const Cand& c) {
   return v;
 }
 
-// Exclusive prefix of the staged candidate counts (region order), for k_cand.
-__global__ __launch_bounds__(NREG) void k_cand_prefix(Regions reg) {
+// Exclusive prefix of the staged candidate counts (region order), for k_cand;
+// with cnt, also the candidate totals (else the compaction writes them).
+__global__ __launch_bounds__(NREG) void k_cand_prefix(Regions reg, Counters* cnt) {
   __shared__ unsigned long long s[NREG];
+  __shared__ unsigned long long s_max[NREG / 64];
   const uint32_t t = threadIdx.x;
   const unsigned long long f = reg.cfill[t * REG_STRIDE];
+  if (cnt) {
+    unsigned long long mx = f;
+    for (int d = 32; d > 0; d >>= 1) {
+      const unsigned long long x = __shfl_xor(mx, d);
+      mx = x > mx ? x : mx;
+    }
+    if ((t & 63) == 0) s_max[t >> 6] = mx;
+  }
+  s[t] = f;
+  __syncthreads();
+  if (cnt && t == 0) {
+    unsigned long long tot = 0, mx = 0;
+    for (uint32_t i = 0; i < NREG; ++i) tot += s[i];
+    for (uint32_t i = 0; i < NREG / 64; ++i) mx = s_max[i] > mx ? s_max[i] : mx;
+    cnt->n_cand = tot;
+    cnt->cand_max = mx;
+  }
+  __syncthreads();
   s[t] = f < reg.Sc ? f : reg.Sc;
   __syncthreads();
   for (uint32_t d = 1; d < NREG; d <<= 1) {
@@ -185,19 +205,63 @@ __global__ __launch_bounds__(NREG) void k_cand_prefix(Regions reg) {
 
 // Every staged candidate, regions in order: ITEMS per thread, their loads
 // in flight together, then the emissions.
-constexpr int CAND_ITEMS = 2;
+constexpr int CAND_ITEMS = 4;
+
+// The pairs of one round of a block (lanes with v[j].in), written straight
+// into the caller's buffer at places taken with one atomic on the pair count
+// per block and round; slots past the capacity are counted, not written.
+// Every thread of the block calls it (two barriers). s_wc and s_base belong
+// to this round; rounds alternate between two sets, so that a wave still
+// reading one round's set is never overtaken by the next round's writes.
+template <int ITEMS>
+__device__ inline void emit_block(const Verdict (&v)[ITEMS], const OutArgs& o, uint32_t* s_wc,
+                                  unsigned long long* s_base) {
+  const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint64_t m[ITEMS];
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    m[j] = __ballot(v[j].in);
+    c += (uint32_t)__popcll(m[j]);
+  }
+  if (lane_id() == 0) s_wc[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (uint32_t i = 0; i < nw; ++i) tot += s_wc[i];
+    *s_base = tot ? atomicAdd(&o.cnt->n_pairs, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long at = *s_base;
+  for (uint32_t i = 0; i < w; ++i) at += s_wc[i];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (v[j].in) {
+      const unsigned long long slot = at + rank_in(m[j]);
+      if (slot < o.cap) {
+        o.pairs[slot] = make_uint2(v[j].ia, v[j].ib);
+        if (o.sep) o.sep[slot] = v[j].sep;
+      }
+    }
+    at += (unsigned long long)__popcll(m[j]);
+  }
+}
 
 template <bool F32, bool HP, int ITEMS>
 __global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
   __shared__ unsigned long long s_pre[NREG + 1];
+  __shared__ uint32_t s_wc[2][256 / 64];
+  __shared__ unsigned long long s_base[2];
   const uint32_t t = threadIdx.x;
   for (uint32_t k = t; k <= NREG; k += blockDim.x) s_pre[k] = o.reg.cpre[k];
   __syncthreads();
   const unsigned long long total = s_pre[NREG];
   const unsigned long long tile = (unsigned long long)ITEMS * blockDim.x;
-  // uniform trip count so every lane of a wave takes part in the ballots
+  uint32_t round = 0;
+  // uniform trip count (the same for the whole block) so every lane takes
+  // part in the ballots and every thread in the barriers
   for (unsigned long long base = (unsigned long long)blockIdx.x * tile; base < total;
-       base += (unsigned long long)gridDim.x * tile) {
+       base += (unsigned long long)gridDim.x * tile, round ^= 1u) {
     Verdict v[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -217,10 +281,16 @@ __global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
         }
       }
     }
+    if (o.direct) {
+      emit_block<ITEMS>(v, o, s_wc[round], &s_base[round]);
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      emit_wave(v[j].in, v[j].ia, v[j].ib, v[j].sep, o);
-      emit_band(v[j].band, v[j].ia, v[j].ib, o);
+      for (int j = 0; j < ITEMS; ++j) emit_band(v[j].band, v[j].ia, v[j].ib, o);
+    } else {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        emit_wave(v[j].in, v[j].ia, v[j].ib, v[j].sep, o);
+        emit_band(v[j].band, v[j].ia, v[j].ib, o);
+      }
     }
   }
 }
@@ -670,7 +740,7 @@ void launch_cand(const MatchArgs& a, const OutArgs& o, bool fp32, hipStream_t s)
   const unsigned long long slots = (unsigned long long)NREG * o.reg.Sc;
   const uint32_t blocks = (uint32_t)std::min<unsigned long long>(
       CAND_BLOCKS_MAX, std::max(1ull, (slots + 256 * CAND_ITEMS - 1) / (256 * CAND_ITEMS)));
-  k_cand_prefix<<<1, NREG, 0, s>>>(o.reg);
+  k_cand_prefix<<<1, NREG, 0, s>>>(o.reg, o.direct ? o.cnt : nullptr);
   if (fp32) k_cand<true, false, CAND_ITEMS><<<blocks, 256, 0, s>>>(a, o);
   else if (a.hp_order >= 0) k_cand<false, true, 1><<<blocks, 256, 0, s>>>(a, o);
   else k_cand<false, false, CAND_ITEMS><<<blocks, 256, 0, s>>>(a, o);

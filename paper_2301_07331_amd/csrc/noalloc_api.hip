@@ -67,10 +67,12 @@ static_assert(sizeof(Counters) <= 256, "counters must fit before the workspace")
 // Staging estimates sized for calls that fit the scratch (the regular
 // call's floors of 4096 slots per region would take most of it); a call
 // that exceeds them runs again with the counted sizes, as hlc_xmatch does.
+// Pairs go straight into the caller's buffer: no pair slots.
 Caps scratch_caps(const ScratchDev& d, uint64_t entries, uint64_t cap) {
+  (void)cap;
   Caps k;
   k.band = 1024 + entries / 64;
-  k.stage = std::max<uint64_t>(cap / NREG + cap / (4 * NREG) + 64, d.hint_stage);
+  k.stage = 0;
   k.cand = std::max<uint64_t>(entries / (2 * NREG) + 64, d.hint_cand);
   return k;
 }

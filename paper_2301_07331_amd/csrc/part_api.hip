@@ -144,7 +144,8 @@ int hlc_xmatch_part(const struct hlc_part* A, const struct hlc_part* B, double r
       std::memset(&g_stats, 0, sizeof(g_stats));
       return HLC_OK;
     }
-    Caps caps = initial_caps(*dev, (uint64_t)A->side.cnt.cap + B->side.cnt.cap, (uint64_t)opts->capacity, true);
+    Caps caps = initial_caps(*dev, (uint64_t)A->side.cnt.cap + B->side.cnt.cap, (uint64_t)opts->capacity, true,
+                             false);
     for (int attempt = 0; attempt < 3; ++attempt) {
       MatchWs w;
       Carve sizing{nullptr};

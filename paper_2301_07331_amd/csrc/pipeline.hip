@@ -74,10 +74,10 @@ uint64_t stage_guess(uint64_t cap) {
   return std::min<uint64_t>(s, 1ull << 22);
 }
 
-Caps initial_caps(const Device& d, uint64_t entries, uint64_t cap, bool stage_cand) {
+Caps initial_caps(const Device& d, uint64_t entries, uint64_t cap, bool stage_cand, bool pair_regions) {
   Caps k;
   k.band = (1u << 20) + entries / 64;
-  k.stage = std::max(stage_guess(cap), d.hint_stage);
+  k.stage = pair_regions ? std::max(stage_guess(cap), d.hint_stage) : 0;
   k.cand = stage_cand ? std::max(std::min<uint64_t>(entries / (2 * NREG) + 4096, 1ull << 22), d.hint_cand) : 0;
   return k;
 }
@@ -86,16 +86,16 @@ void carve_regions(Carve& c, Regions& r, const Caps& k, bool sep) {
   r.fill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
   r.cfill = c.take<unsigned long long>((size_t)NREG * REG_STRIDE);
   r.S = k.stage;
-  r.pairs = c.take<uint2>((size_t)NREG * k.stage);
-  r.sep = sep ? c.take<double>((size_t)NREG * k.stage) : nullptr;
+  r.pairs = k.stage ? c.take<uint2>((size_t)NREG * k.stage) : nullptr;
+  r.sep = (sep && k.stage) ? c.take<double>((size_t)NREG * k.stage) : nullptr;
   r.Sc = k.cand;
   r.cand = k.cand ? c.take<Cand>((size_t)NREG * k.cand) : nullptr;
   r.cpre = c.take<unsigned long long>((size_t)NREG + 1);
 }
 
 // True when the call must run again: its band list overflowed, a candidate
-// region overflowed, or a pair region overflowed although the caller's
-// buffer holds every pair.
+// region overflowed, or a pair region (if pairs are staged) overflowed
+// although the caller's buffer holds every pair.
 bool regrow(Device& d, const Counters& h, uint64_t cap, Caps& k) {
   bool again = false;
   if (h.n_band > k.band) {
@@ -107,7 +107,7 @@ bool regrow(Device& d, const Counters& h, uint64_t cap, Caps& k) {
     d.hint_cand = std::max(d.hint_cand, k.cand);
     again = true;
   }
-  if (!again && h.n_pairs <= cap && h.region_max > k.stage) {
+  if (!again && k.stage && h.n_pairs <= cap && h.region_max > k.stage) {
     k.stage = h.region_max + h.region_max / 8 + 1024;
     d.hint_stage = std::max(d.hint_stage, k.stage);
     again = true;
@@ -154,7 +154,9 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   launch_ranges(A.keys, A.cnt, w.kidx, ki.shift, ki.T, B.keys, zstart, w.zmarg, w.zdelta, g, w.ranges, ps);
   if (prof >= PROF_ALL) (void)hipEventRecord(dev.ev[8], ps);
   // the candidate regions are cleared before the join, beside the ranges
-  const OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
+  // certified pairs go straight into the caller's buffer (no pair regions)
+  OutArgs oa = out_args(out_pairs, out_sep, cap, w.band, w.band_cap, w.reg, dev.cnt);
+  oa.direct = 1;
   launch_regions_reset(oa, s);
   // The filter and what follows run on ps after the ranges, once B's records
   // are gathered on s (that event is usually complete by then, so the join
@@ -200,7 +202,6 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   if (prof) (void)hipEventRecord(dev.ev[9], ts);
   launch_cand(ma, oa, fp32, ts);
   launch_certify(A.ra, A.dec, B.ra, B.dec, r_arcsec, th.H_lo, th.H_hi, rad, oa, ts);
-  launch_compact(oa, ts);
   if (prof >= PROF_ALL) (void)hipEventRecord(dev.ev[10], ts);
 }
 

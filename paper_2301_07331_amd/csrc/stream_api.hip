@@ -373,7 +373,7 @@ int stream_impl(const double* a_ra_h, const double* a_dec_h, int64_t na, const d
       return HLC_E_INVAL;
     return HLC_OK;
   };
-  Caps caps = initial_caps(*dev, 2 * (uint64_t)SLAB, (uint64_t)half, true);
+  Caps caps = initial_caps(*dev, 2 * (uint64_t)SLAB, (uint64_t)half, true, false);
   for (int64_t k = 0; k < nslab; ++k) {
     const int b = (int)(k & 1);
     const int64_t a0 = k * SLAB, m = std::min(SLAB, na - a0);

@@ -143,7 +143,7 @@ int xmatch_core(const double* a_ra, const double* a_dec, int64_t na, const doubl
                 double* out_sep, const hlc_opts* o, const Radii& rad = Radii{nullptr, nullptr, 0.0}) {
   Device* dev = nullptr;
   HLC_CHECK(get_device(&dev));
-  Caps caps = initial_caps(*dev, (uint64_t)(na + nb), (uint64_t)o->capacity, true);
+  Caps caps = initial_caps(*dev, (uint64_t)(na + nb), (uint64_t)o->capacity, true, false);
   for (int attempt = 0; attempt < 3; ++attempt) {
     bool again = false;
     int st = xmatch_impl(a_ra, a_dec, na, b_ra, b_dec, nb, r_arcsec, out_pairs, out_sep, o, caps, &again, rad);
@@ -240,7 +240,7 @@ int hlc_xmatch_quad(const double* a_ra, const double* a_dec, int64_t na, const d
     HLC_CHECK(get_device(&dev));
     hipStream_t s = (hipStream_t)opts->stream;
     const uint32_t capA = 5u * (uint32_t)na, capB = 5u * (uint32_t)nb;
-    Caps caps = initial_caps(*dev, (uint64_t)capA + capB, (uint64_t)opts->capacity, true);
+    Caps caps = initial_caps(*dev, (uint64_t)capA + capB, (uint64_t)opts->capacity, true, true);
     for (int attempt = 0; attempt < 3; ++attempt) {
       Side A, B;
       SortScratch sc;

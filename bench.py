@@ -48,7 +48,7 @@ VALU_ISSUE_PER_S = 256 * 4 * 2.4e9
 # (FETCH_SIZE and WRITE_SIZE passes, scaled by a 1 GiB copy) and recorded
 # with a hash of the kernel sources it was measured on; reported only while
 # the sources are unchanged.
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_k_filter_fullsky_10Mx10M_r2.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_k_filter_fullsky_10Mx10M_2arcsec.md")
 KERNEL_SOURCES = ["match.hip", "hlc_device.hpp", "hlc_kernels.hpp"]
 
 

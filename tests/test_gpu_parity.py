@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import assert_same, gpu_xmatch, to_dev
+from tests.gpu_util import SEP_TOL_ARCSEC, assert_same, gpu_xmatch, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -141,6 +141,35 @@ def test_overflow_reports_required_count(hlc, prec):
     # HLC_NO_SEP: no separation buffer needed
     st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, None, precision=prec, flags=hlc.HLC_NO_SEP)
     assert st == hlc.HLC_OK and n == len(ref)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_overflow_writes_within_capacity(hlc, prec):
+    """A call whose pairs exceed its capacity fills exactly the capacity's
+    slots with distinct true pairs (their separations the oracle's) and
+    writes nothing past them."""
+    import torch
+    c = synth.patch_pair(scale=0.2, seed_sub=3)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    rk = ref.keys()
+    order = np.argsort(rk)
+    rk, rsep = rk[order], ref.sep[order]
+    args = [to_dev(x) for x in (c.a_ra, c.a_dec, c.b_ra, c.b_dec)]
+    pad = 257
+    for cap in (1, 777, len(ref) // 2, len(ref) - 1):
+        out = torch.full((cap + pad, 2), -7, dtype=torch.int32, device="cuda")
+        sep = torch.full((cap + pad,), -7.0, dtype=torch.float64, device="cuda")
+        st, n = hlc.hlc_xmatch(*args, c.r_arcsec, out, sep, precision=prec, capacity=cap)
+        assert st == hlc.HLC_E_OVERFLOW and n == len(ref), (cap, st, n)
+        o, s_ = out.cpu().numpy(), sep.cpu().numpy()
+        assert np.all(o[cap:] == -7) and np.all(s_[cap:] == -7.0), f"cap {cap}: written past the capacity"
+        p = o[:cap].view(np.uint32)
+        keys = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+        assert len(np.unique(keys)) == cap, f"cap {cap}: duplicate pairs"
+        at = np.searchsorted(rk, keys)
+        assert np.all(at < len(rk)) and np.array_equal(rk[np.minimum(at, len(rk) - 1)], keys), \
+            f"cap {cap}: pairs that are not matches"
+        assert np.max(np.abs(s_[:cap] - rsep[at])) <= SEP_TOL_ARCSEC
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)

@@ -59,6 +59,32 @@ def test_parts_reuse_both_roles(hlc, prec):
     PB.free()
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_part_overflow(hlc, prec):
+    """Reused partitions: a capacity below the pair count reports the
+    required count and writes true pairs into exactly its slots."""
+    import torch
+    c = synth.patch_pair(scale=0.3, seed_sub=11)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, 2.0)
+    rk = np.sort(ref.keys())
+    st, PA = hlc.hlc_partition(to_dev(c.a_ra), to_dev(c.a_dec), 2.0)
+    assert st == hlc.HLC_OK
+    st, PB = hlc.hlc_partition(to_dev(c.b_ra), to_dev(c.b_dec), 2.0)
+    assert st == hlc.HLC_OK
+    cap, pad = len(ref) // 3, 100
+    out = torch.full((cap + pad, 2), -7, dtype=torch.int32, device="cuda")
+    sep = torch.full((cap + pad,), -7.0, dtype=torch.float64, device="cuda")
+    st, n = hlc.hlc_xmatch_part(PA, PB, 2.0, out, sep, precision=prec, capacity=cap)
+    assert st == hlc.HLC_E_OVERFLOW and n == len(ref)
+    o = out.cpu().numpy()
+    assert np.all(o[cap:] == -7) and np.all(sep[cap:].cpu().numpy() == -7.0)
+    p = o[:cap].view(np.uint32)
+    keys = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+    assert len(np.unique(keys)) == cap and np.all(np.isin(keys, rk))
+    PA.free()
+    PB.free()
+
+
 def test_part_errors(hlc):
     import torch
     g = synth.rng(300, 0)

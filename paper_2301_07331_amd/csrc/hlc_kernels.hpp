@@ -42,6 +42,9 @@ void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& 
 uint32_t keygen_hist_tiles(uint32_t n);
 void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s);
 void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* src, CellRec32* rec, hipStream_t s);
+// sorted cell records and sorted (ra, dec) (radec may be null) from 32-B per-source records
+void launch_gather32_radec(const uint32_t* vals, const DevCount& n, const SrcRec32* src, CellRec32* rec,
+                           double2* radec, hipStream_t s);
 
 size_t sort_counts_len(uint32_t n);
 size_t sort_digit_totals_len(uint32_t n);
@@ -81,8 +84,9 @@ void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const 
                               double* zdelta = nullptr);
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
                      Rec64* rec, hipStream_t s);
+// (and the sorted (ra, dec) when radec is not null)
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     CellRec32* rec, hipStream_t s);
+                     CellRec32* rec, double2* radec, hipStream_t s);
 // radec[i] = (ra[i], dec[i]), i < n
 void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s);
 // lb[i] = number of B keys below keysA[i]; splits: merge_splits_len words of scratch
@@ -113,11 +117,17 @@ constexpr int REG_STRIDE = 32;  // u64 slots between two region counters
 //     with it, so the certification reads nothing of A: (u0, u1, u2) is A's
 //     FP64 unit vector, ia A's original index (paper-scheme emulation: A's
 //     sorted position), b B's sorted position.
-//   FP32 form: (u0, u1) is A's (ra, dec) when the filter read it with A's
-//     record (A read in place), else NaN; ia and b are A's and B's original
-//     indices; the certification reads B's (ra, dec) by index.
+//   FP32 form: (u0, u1) is A's (ra, dec) when the filter has it (A read in
+//     place, or A's (ra, dec) sorted), else NaN; ia and b are A's and B's
+//     original indices, bpos B's sorted position; the certification reads
+//     B's (ra, dec) at bpos when they are sorted (the candidates of one wave
+//     lie in a few B windows, so those reads share cache lines), else by b.
 struct Cand {
-  double u0, u1, u2;
+  double u0, u1;
+  union {
+    double u2;      // FP64 form
+    uint32_t bpos;  // FP32 form
+  };
   uint32_t ia, b;
 };
 
@@ -199,14 +209,15 @@ struct MatchArgs {
   const Rec64* recB64;
   double t_lo64, t_hi64;        // chord^2: certain in / candidate
   // FP32 form: sorted cell records, and the FP64 (ra, dec) of each source by
-  // original index (certification; srcradA may be null when A is read in
-  // place, its candidates then carry A's (ra, dec))
+  // original index (certification; null when A is read in place, its
+  // candidates then carry A's (ra, dec), or when the side has them sorted)
   const CellRec32* recA32;
   const CellRec32* recB32;
   const double2* srcradA;
   const double2* srcradB;
   float c_r32;                  // chord of r, rounded up to FP32
-  // paper-scheme emulation: the FP64 (ra, dec) of every sorted entry
+  // the FP64 (ra, dec) of every sorted entry, or null: FP32 certification in
+  // the sorted layout, and the paper-scheme emulation
   const double2* radecA;
   const double2* radecB;
   // sorted index arrays (source index, halo bit included)

@@ -53,6 +53,10 @@ struct Device {
   // staging sizes that earlier calls needed (grow-only), so a repeated
   // workload does not pay the overflow re-run again
   uint64_t hint_stage = 0, hint_cand = 0;
+  // FP32 candidates per B entry of the last FP32 single call: at
+  // SORTED_RADEC_MIN or more the next one uses the sorted certification
+  // layout for B (see carve_side)
+  double cand_per_b = 0.0;
   int ncu = 0;  // compute units (persistent grids)
   bool last_full = true;  // the last call's frame was the whole sphere
   // the footprint sample's result, written by the kernel into mapped host
@@ -222,13 +226,17 @@ struct Side {
   uint32_t *keys = nullptr, *vals = nullptr;
   Rec64* r64 = nullptr;
   CellRec32* r32 = nullptr;
-  double2* radec = nullptr;   // sorted (ra, dec) (paper-scheme emulation only)
+  // sorted (ra, dec): FP32 form in the sorted certification layout (see
+  // carve_side), and the paper-scheme emulation's pixel tests
+  double2* radec = nullptr;
   // per-source records written by the keygen in input order (nullptr: the
   // layout computes the sorted records from the coordinates)
   Rec64* src64 = nullptr;     // FP64 form
   CellRec32* cell32 = nullptr;  // FP32 form, gathered side: cell records
   double2* srcrad = nullptr;  // FP32 form, gathered side: (ra, dec) by original index
-  SrcRec32* src32 = nullptr;  // FP32 form, side read in place: cell record + (ra, dec)
+  // FP32 form: cell record + (ra, dec); a side read in place, or a gathered
+  // side in the sorted certification layout
+  SrcRec32* src32 = nullptr;
   const double *ra = nullptr, *dec = nullptr;  // original coordinates (for the band list)
 };
 
@@ -262,6 +270,13 @@ int partition(Device& dev, const double* ra, const double* dec, uint32_t n, cons
 // (never finer than the sorted key bits: the low fb bits of a sorted key
 // array are in input order within a bin, so the index is exact only on
 // multiples of 2^fb)
+// Below about two FP32 candidates per B entry, reading each candidate's B
+// (ra, dec) at random from a 16-B array in input order costs less than
+// gathering every entry's into sorted order (measured at 10M x 10M,
+// 0.4 per entry: 10 us slower with the gather; at 20M x 20M, 8.7 per entry:
+// 0.35-0.5 ms faster).
+constexpr double SORTED_RADEC_MIN = 2.0;
+
 struct KeyIndex {
   int shift;
   uint32_t T;
@@ -321,8 +336,15 @@ inline int prof_level(uint32_t flags) {
 size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, const Caps& caps,
                       bool need_zstart);
 // cap entries; n_src > 0 also carves the per-source records of the keygen;
-// without `layout` no sorted records are carved (the side is read in place)
-void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src = 0, bool layout = true);
+// without `layout` no sorted records are carved (the side is read in place).
+// FP32, gathered: with sorted_radec the sorted certification layout (32-B
+// per-source records, gathered into sorted cell records and sorted (ra, dec):
+// the certification reads a candidate's B (ra, dec) at its sorted position),
+// else 16-B cell records and (ra, dec) in separate input-order arrays (the
+// gather and the certification then read at random from arrays half the
+// size).
+void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src = 0, bool layout = true,
+                bool sorted_radec = false);
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax);
 
 // the coordinates checked (no pairs: one side is empty)

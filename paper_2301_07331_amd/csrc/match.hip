@@ -152,7 +152,8 @@ __device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
 __device__ inline Verdict certify32(const MatchArgs& a, const Cand& c) {
   Verdict v{false, false, 0u, 0u, 0.0};
   const uint32_t ia = c.ia, ib = c.b;
-  const double2 pb = a.srcradB[ib];
+  // B's (ra, dec) at its sorted position when sorted, else by original index
+  const double2 pb = a.radecB ? a.radecB[c.bpos] : a.srcradB[ib];
   const double2 pa = (c.u0 == c.u0) ? make_double2(c.u0, c.u1) : a.srcradA[ia];
   v.ia = ia;
   v.ib = ib;
@@ -329,11 +330,22 @@ __device__ inline void stage_candidates(const MatchArgs& a, const OutArgs& o, co
       const unsigned long long slot = base + rank_in(m);
       const unsigned long long at = (unsigned long long)k * o.reg.Sc + slot;
       if (slot < o.reg.Sc) {
-        // FP32 form: A's (ra, dec) (NaN: not at hand) and the two original
-        // indices (the halo bit dropped); FP64: A's unit vector, A's index
-        // and B's position
-        if constexpr (F32) o.reg.cand[at] = Cand{A.u0, A.u1, 0.0, A.ia, a.valsB[ent.y] & IDX_MASK};
-        else o.reg.cand[at] = Cand{A.u0, A.u1, A.u2, A.ia, ent.y};
+        // FP32 form: A's (ra, dec) (NaN: not at hand), B's position and the
+        // two original indices (the halo bit dropped); FP64: A's unit
+        // vector, A's index and B's position
+        Cand c;
+        c.u0 = A.u0;
+        c.u1 = A.u1;
+        c.ia = A.ia;
+        if constexpr (F32) {
+          c.u2 = 0.0;
+          c.bpos = ent.y;
+          c.b = a.valsB[ent.y] & IDX_MASK;
+        } else {
+          c.u2 = A.u2;
+          c.b = ent.y;
+        }
+        o.reg.cand[at] = c;
       }
     }
   }
@@ -487,7 +499,13 @@ __device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
       r.u1 = s.dec;
     } else {
       r.ca = a.recA32[h.a_pos];
-      r.u0 = __builtin_nan("");  // the certification reads A's (ra, dec)
+      if (a.radecA) {
+        const double2 p = a.radecA[h.a_pos];
+        r.u0 = p.x;
+        r.u1 = p.y;
+      } else {
+        r.u0 = __builtin_nan("");  // the certification reads A's (ra, dec)
+      }
     }
   } else {
     const Rec64 s = a.a_in_place ? a.srcA64[idx & IDX_MASK] : a.recA64[h.a_pos];

@@ -47,8 +47,9 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     p->g = make_geom(r_arcsec, h_as, n, n, tuned_bins(opts));
     const uint32_t nn = (uint32_t)n, cap = 2 * nn;
     auto lay = [&](Carve& c) {
-      carve_side(c, p->side, cap, true, true);
-      p->side.srcrad = c.take<double2>(std::max(nn, 1u));  // FP32 certification, kept
+      // FP32: sorted (ra, dec) kept with the part for the certification (its
+      // per-source records are scratch)
+      carve_side(c, p->side, cap, true, true, 0, true, true);
       p->zstart = c.take<uint32_t>((size_t)p->g.nz + 1);
       p->ra = c.take<double>(std::max(nn, 1u));
       p->dec = c.take<double>(std::max(nn, 1u));
@@ -68,7 +69,7 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     auto scratch = [&](Carve& c) {
       carve_sort(c, sc, std::max(cap, 1u));
       p->side.src64 = c.take<Rec64>(std::max(nn, 1u));
-      p->side.cell32 = c.take<CellRec32>(std::max(nn, 1u));
+      p->side.src32 = c.take<SrcRec32>(std::max(nn, 1u));
     };
     Carve ss{nullptr};
     scratch(ss);
@@ -86,7 +87,7 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     launch_zero_counters(dev->cnt, s);
     st = partition(*dev, p->ra, p->dec, nn, p->g, true, true, true, sc, 1u, p->side, NO_SLOTS, s);
     p->side.src64 = nullptr;
-    p->side.cell32 = nullptr;
+    p->side.src32 = nullptr;
     if (st == HLC_OK) {
       launch_zone_starts(p->side.keys, p->side.cnt, p->g, p->zstart, s);
       st = read_counters(*dev, s, false);

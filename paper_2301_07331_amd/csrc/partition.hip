@@ -497,17 +497,20 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
   rec[p] = r;
 }
 
-// FP32 cell record of the FP64 unit vector, from the caller's coordinates
+// FP32 cell record of the FP64 unit vector (and, with radec, the (ra, dec)),
+// sorted, from the caller's coordinates
 __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
-                                                  CellRec32* __restrict__ rec) {
+                                                  CellRec32* __restrict__ rec, double2* __restrict__ radec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc.get()) return;
   uint32_t i = vals[p] & IDX_MASK;
+  const double a = ra[i], d = dec[i];
   double x, y, z;
-  unit_vector(ra[i], dec[i], x, y, z);
+  unit_vector(a, d, x, y, z);
   rec[p] = encode_cell(x, y, z);
+  if (radec) radec[p] = make_double2(a, d);
 }
 
 // (ra, dec) of each source interleaved, in input order
@@ -538,6 +541,20 @@ __global__ __launch_bounds__(256) void k_gather32(const uint32_t* __restrict__ v
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc.get()) return;
   rec[p] = src[vals[p] & IDX_MASK];
+}
+
+// Sorted cell records and sorted (ra, dec) from the keygen's 32-B
+// per-source records (one random line per entry for both), for a
+// certification that reads a candidate's B (ra, dec) at its sorted position,
+// where the other candidates of its group read too.
+__global__ __launch_bounds__(256) void k_gather32_radec(const uint32_t* __restrict__ vals, DevCount nc,
+                                                        const SrcRec32* __restrict__ src,
+                                                        CellRec32* __restrict__ rec, double2* __restrict__ radec) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc.get()) return;
+  const SrcRec32& r = src[vals[p] & IDX_MASK];
+  rec[p] = r.c;
+  if (radec) radec[p] = make_double2(r.ra, r.dec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,6 +1173,12 @@ void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* s
   k_gather32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
 }
 
+void launch_gather32_radec(const uint32_t* vals, const DevCount& n, const SrcRec32* src, CellRec32* rec,
+                           double2* radec, hipStream_t s) {
+  if (n.cap == 0) return;
+  k_gather32_radec<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec, radec);
+}
+
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
 size_t sort_digit_totals_len(uint32_t n) { (void)n; return RS_BINS; }
 
@@ -1249,9 +1272,9 @@ void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, 
 }
 
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     CellRec32* rec, hipStream_t s) {
+                     CellRec32* rec, double2* radec, hipStream_t s) {
   if (n.cap == 0) return;
-  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
+  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec, radec);
 }
 
 void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s) {

@@ -53,8 +53,10 @@ int partition_sort(Device& dev, const Geom& g, bool l64, bool l32, const SortScr
   if (l32 && sd.r32) {
     if (sd.cell32) {
       launch_gather32(sd.vals, sd.cnt, sd.cell32, sd.r32, s);
+    } else if (sd.src32) {
+      launch_gather32_radec(sd.vals, sd.cnt, sd.src32, sd.r32, sd.radec, s);
     } else {
-      launch_layout32(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r32, s);
+      launch_layout32(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r32, sd.radec, s);
       if (sd.srcrad) launch_interleave(sd.ra, sd.dec, sd.n_src, sd.srcrad, s);
     }
   }
@@ -179,6 +181,8 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.recB32 = B.r32;
   ma.srcradA = A.srcrad;
   ma.srcradB = B.srcrad;
+  ma.radecA = A.radec;
+  ma.radecB = B.radec;
   ma.keysA = A.keys;
   ma.keysB = B.keys;
   ma.c_r32 = th.c_r32;
@@ -224,20 +228,23 @@ size_t carve_match_ws(Carve& c, MatchWs& w, uint32_t na_entries, const Geom& g, 
 
 // cap entries; n_src > 0 also carves the per-source records of the keygen;
 // without `layout` no sorted records are carved (the side is read in place)
-void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src, bool layout) {
+void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n_src, bool layout,
+                bool sorted_radec) {
   cap = std::max(cap, 1u);
   sd.keys = c.take<uint32_t>(cap);
   sd.vals = c.take<uint32_t>(cap);
   sd.r64 = (l64 && layout) ? c.take<Rec64>(cap) : nullptr;
   sd.r32 = (l32 && layout) ? c.take<CellRec32>(cap) : nullptr;
-  sd.radec = nullptr;
+  const bool sorted = l32 && layout && sorted_radec;
+  sd.radec = sorted ? c.take<double2>(cap) : nullptr;
   sd.src64 = (l64 && n_src) ? c.take<Rec64>(n_src) : nullptr;
   // FP32: a gathered side keeps cell records and (ra, dec) apart (the gather
-  // then reads from an array half the size); a side read in place keeps them
-  // together (one cache line per entry for both)
-  sd.cell32 = (l32 && n_src && layout) ? c.take<CellRec32>(n_src) : nullptr;
-  sd.srcrad = (l32 && n_src && layout) ? c.take<double2>(n_src) : nullptr;
-  sd.src32 = (l32 && n_src && !layout) ? c.take<SrcRec32>(n_src) : nullptr;
+  // then reads from an array half the size), unless its (ra, dec) are
+  // gathered too; a side read in place keeps them together (one cache line
+  // per entry for both)
+  sd.cell32 = (l32 && n_src && layout && !sorted) ? c.take<CellRec32>(n_src) : nullptr;
+  sd.srcrad = (l32 && n_src && layout && !sorted) ? c.take<double2>(n_src) : nullptr;
+  sd.src32 = (l32 && n_src && (!layout || sorted)) ? c.take<SrcRec32>(n_src) : nullptr;
 }
 
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {

@@ -38,13 +38,16 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   Side A, B;
   SortScratch sc, scA;
   MatchWs w;
+  // FP32: B in the sorted certification layout when the last FP32 call on
+  // this device had that many candidates per B entry
+  const bool sorted_b = fp32 && dev->cand_per_b >= SORTED_RADEC_MIN;
   auto lay = [&](Carve& c) {
     // A is read in place: the filter gathers its records itself
     if (!self) {
       carve_side(c, A, nA, !fp32, fp32, nA, false);
       carve_sort(c, scA, nA);
     }
-    carve_side(c, B, 2 * nB, !fp32, fp32, nB);
+    carve_side(c, B, 2 * nB, !fp32, fp32, nB, true, sorted_b);
     carve_sort(c, sc, 2 * nB);
     carve_match_ws(c, w, nA, g, caps, true);
   };
@@ -133,6 +136,7 @@ int xmatch_impl(const double* a_ra, const double* a_dec, int64_t na, const doubl
   fill_stats(h, na, nb, nb + (int64_t)h.n_halo, g);
   if (prof) fill_times(*dev, true);
   else if (plevel == PROF_FILTER) g_stats.t_match_ms = elapsed(dev->ev[13], dev->ev[9]);
+  if (fp32) dev->cand_per_b = (double)h.n_cand / (double)std::max<unsigned long long>(1, nb + h.n_halo);
   *o->n_pairs = (int64_t)h.n_pairs;
   return h.n_pairs > (unsigned long long)o->capacity ? HLC_E_OVERFLOW : HLC_OK;
 }

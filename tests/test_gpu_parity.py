@@ -344,6 +344,42 @@ def test_self_match(hlc, prec):
     assert st == hlc.HLC_E_INVAL
 
 
+def test_dense_fp32_sorted_radec(hlc):
+    """FP32 calls on dense data: after a call with many candidates per B
+    entry the library gathers B's (ra, dec) into sorted order for the
+    certification instead of reading them by original index; the first call
+    (by index) and the later ones (sorted), a self-match and a sparse call
+    after them all match the oracle."""
+    g = synth.rng(640, 0)
+    a_ra, a_dec = synth.uniform_patch(g, 50_000, 150.0, 150.05, 2.0, 2.05)
+    b_ra, b_dec = synth.uniform_patch(g, 50_000, 150.0, 150.05, 2.0, 2.05)
+    r = 1.5
+    ref = oracle.xmatch(a_ra, a_dec, b_ra, b_dec, r)
+    for call in range(3):
+        keys, sep = gpu_xmatch(a_ra, a_dec, b_ra, b_dec, r, 0)
+        assert_same(keys, sep, ref, label=f"dense call {call}")
+        st = hlc.last_stats()
+        assert st["n_candidates"] >= 2 * st["nb_halo"], st  # (B entries, halo copies included)
+    # a self-match in the sorted form (A is B: A's (ra, dec) from the sorted array)
+    full = oracle.xmatch(b_ra, b_dec, b_ra, b_dec, r)
+    keep = full.a < full.b
+    R = type("R", (), {})()
+    R.keys = lambda: full.keys()[keep]
+    R.sep = full.sep[keep]
+    t_ra, t_dec = to_dev(b_ra), to_dev(b_dec)
+    pairs, sep = hlc.xmatch(t_ra, t_dec, t_ra, t_dec, r, precision=0, flags=hlc.HLC_SELF)
+    p = pairs.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    k = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+    order = np.argsort(k)
+    assert_same(k[order], sep.cpu().numpy()[order], R, label="dense self")
+    # a sparse call right after (sorted form, as the last call was dense), then by index again
+    c = synth.patch_pair(scale=0.2, seed_sub=9)
+    ref = oracle.xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec)
+    for call in range(2):
+        keys, sep = gpu_xmatch(c.a_ra, c.a_dec, c.b_ra, c.b_dec, c.r_arcsec, 0)
+        assert_same(keys, sep, ref, label=f"sparse call {call}")
+
+
 @pytest.mark.parametrize("prec", PRECISIONS)
 def test_error_radii(hlc, prec):
     """Eq. (4): theta <= 3 sqrt(ea^2 + eb^2), per pair, against the oracle."""

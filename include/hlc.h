@@ -32,6 +32,10 @@
  *     a caller pointer after a call returns.
  *   - The library owns a per-device workspace, grown on demand and released
  *     by hlc_shutdown(), and every hlc_part it hands out.
+ *   - A call on a device sizes its staging buffers, and (FP32) chooses how
+ *     it lays out B's coordinates for the certification, from what earlier
+ *     calls on that device counted; results never depend on this, only the
+ *     time does.
  *
  * Errors: every int-returning call returns HLC_OK (0) or a negative
  * hlc_status; no C++ exception crosses this boundary. HIP runtime failures

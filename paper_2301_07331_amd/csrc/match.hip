@@ -114,15 +114,15 @@ __device__ inline void emit_band(bool band, uint32_t ia, uint32_t ib, const OutA
 // ---------------------------------------------------------------------------
 // certification of one staged candidate
 // ---------------------------------------------------------------------------
-struct Verdict {
+struct Decision {
   bool in, band;
   uint32_t ia, ib;
   double sep;
 };
 
 template <bool HP>
-__device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
-  Verdict v{false, false, 0u, 0u, 0.0};
+__device__ inline Decision certify64(const MatchArgs& a, const Cand& c) {
+  Decision v{false, false, 0u, 0u, 0.0};
   const Rec64 B = a.recB64[c.b];
   const double dx = c.u0 - B.x, dy = c.u1 - B.y, dz = c.u2 - B.z;
   const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -149,8 +149,8 @@ __device__ inline Verdict certify64(const MatchArgs& a, const Cand& c) {
   return v;
 }
 
-__device__ inline Verdict certify32(const MatchArgs& a, const Cand& c) {
-  Verdict v{false, false, 0u, 0u, 0.0};
+__device__ inline Decision certify32(const MatchArgs& a, const Cand& c) {
+  Decision v{false, false, 0u, 0u, 0.0};
   const uint32_t ia = c.ia, ib = c.b;
   // B's (ra, dec) at its sorted position when sorted, else by original index
   const double2 pb = a.radecB ? a.radecB[c.bpos] : a.srcradB[ib];
@@ -215,7 +215,7 @@ constexpr int CAND_ITEMS = 4;
 // to this round; rounds alternate between two sets, so that a wave still
 // reading one round's set is never overtaken by the next round's writes.
 template <int ITEMS>
-__device__ inline void emit_block(const Verdict (&v)[ITEMS], const OutArgs& o, uint32_t* s_wc,
+__device__ inline void emit_block(const Decision (&v)[ITEMS], const OutArgs& o, uint32_t* s_wc,
                                   unsigned long long* s_base) {
   const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   uint64_t m[ITEMS];
@@ -263,11 +263,11 @@ __global__ __launch_bounds__(256) void k_cand(MatchArgs a, OutArgs o) {
   // part in the ballots and every thread in the barriers
   for (unsigned long long base = (unsigned long long)blockIdx.x * tile; base < total;
        base += (unsigned long long)gridDim.x * tile, round ^= 1u) {
-    Verdict v[ITEMS];
+    Decision v[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const unsigned long long i = base + (unsigned long long)j * blockDim.x + t;
-      v[j] = Verdict{false, false, 0u, 0u, 0.0};
+      v[j] = Decision{false, false, 0u, 0u, 0.0};
       if (i < total) {
         uint32_t lo = 0, hi = NREG;  // region k with s_pre[k] <= i < s_pre[k + 1]
         while (hi - lo > 1) {

@@ -257,7 +257,10 @@ __host__ __device__ inline void sincos_small(double r, double* s, double* c) {
 // sin and cos of an angle in degrees, |x| <= 360.
 // The argument is reduced by the nearest multiple of 90 degrees, which is
 // exact in FP64 for |x| <= 360 (Sterbenz), converted to radians with a
-// double-double pi/180, and the quadrant is applied by swapping/negating.
+// double-double pi/180, and the quadrant is applied by swapping/negating:
+// quadrant q gives (sin, cos) = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr)
+// for q = 0, 1, 2, 3 (selects, no branches: the quadrants of a wave's
+// lanes differ).
 // ---------------------------------------------------------------------------
 __device__ inline void sincos_deg(double x, double* s, double* c) {
   double q = rint(x * (1.0 / 90.0));
@@ -267,11 +270,11 @@ __device__ inline void sincos_deg(double x, double* s, double* c) {
   double r = p + fma(y, DEG2RAD_LO, e);
   double sr, cr;
   sincos_small(r, &sr, &cr);
-  int qi = ((int)q) & 3;
-  if (qi == 0) { *s = sr; *c = cr; }
-  else if (qi == 1) { *s = cr; *c = -sr; }
-  else if (qi == 2) { *s = -sr; *c = -cr; }
-  else { *s = -cr; *c = sr; }
+  const int qi = ((int)q) & 3;
+  const double s0 = (qi & 1) ? cr : sr;
+  const double c0 = (qi & 1) ? sr : cr;
+  *s = (qi & 2) ? -s0 : s0;
+  *c = ((qi + 1) & 2) ? -c0 : c0;
 }
 
 __device__ inline double cos_deg_abs(double dec) {

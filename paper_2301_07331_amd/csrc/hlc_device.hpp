@@ -277,6 +277,17 @@ __device__ inline void sincos_deg(double x, double* s, double* c) {
   *c = ((qi + 1) & 2) ? -c0 : c0;
 }
 
+// unit vector of (ra, dec) in degrees; the keygen and the FP32 filter of a
+// side read in place use this one sequence, so their cell records agree
+__device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
+  double sd, cd, sa, ca;
+  sincos_deg(dec, &sd, &cd);
+  sincos_deg(ra, &sa, &ca);
+  x = cd * ca;
+  y = cd * sa;
+  z = sd;
+}
+
 __device__ inline double cos_deg_abs(double dec) {
   // cos of a declination, relatively accurate near the poles
   double a = fabs(dec);

@@ -224,7 +224,9 @@ struct MatchArgs {
   const uint32_t* valsA;
   const uint32_t* valsB;
   // A read in place (recA64 / recA32 unused): entry p's record is the
-  // keygen's per-source record of source valsA[p]
+  // keygen's per-source record of source valsA[p] (srcA64 / srcA32), or when
+  // that is null only the (ra, dec) in srcradA, from which the filter
+  // derives the unit vector or cell record
   int a_in_place;
   const Rec64* srcA64;
   const SrcRec32* srcA32;

@@ -231,11 +231,13 @@ struct Side {
   double2* radec = nullptr;
   // per-source records written by the keygen in input order (nullptr: the
   // layout computes the sorted records from the coordinates)
-  Rec64* src64 = nullptr;     // FP64 form
+  Rec64* src64 = nullptr;     // FP64 form, gathered side
   CellRec32* cell32 = nullptr;  // FP32 form, gathered side: cell records
-  double2* srcrad = nullptr;  // FP32 form, gathered side: (ra, dec) by original index
-  // FP32 form: cell record + (ra, dec); a side read in place, or a gathered
-  // side in the sorted certification layout
+  // (ra, dec) by original index: FP32 form, gathered side (for the
+  // certification); either form, a side read in place (its only record)
+  double2* srcrad = nullptr;
+  // FP32 form: cell record + (ra, dec); a gathered side in the sorted
+  // certification layout (and the reusable partitions)
   SrcRec32* src32 = nullptr;
   const double *ra = nullptr, *dec = nullptr;  // original coordinates (for the band list)
 };

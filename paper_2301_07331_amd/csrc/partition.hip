@@ -87,21 +87,15 @@ constexpr uint32_t KG_THREADS = 512;
 constexpr uint32_t KG_TILE = KG_ITEMS * KG_THREADS;
 static_assert(KG_TILE == (uint32_t)RS_TILE, "a keygen block fills one radix tile");
 
-__device__ inline void unit_vector(double ra, double dec, double& x, double& y, double& z) {
-  double sd, cd, sa, ca;
-  sincos_deg(dec, &sd, &cd);
-  sincos_deg(ra, &sa, &ca);
-  x = cd * ca;
-  y = cd * sa;
-  z = sd;
-}
-
 // Besides the keys, each source's working record is written in input order
-// (coalesced): the FP64 record (unit vector and index, 32 B), or for the
-// FP32 form the 16-B cell record and, in a second array, the FP64 (ra, dec)
-// that certifies candidates. The layout after the sort is then a single
-// gather of one record per entry, from an array a quarter the size of the
-// line traffic of two 8-B gathers of (ra, dec) from the caller's arrays.
+// (coalesced). A side that is gathered after its sort gets the FP64 record
+// (unit vector and index, 32 B), or for the FP32 form the 16-B cell record
+// and, in a second array, the FP64 (ra, dec) that certifies candidates; its
+// layout is then a single gather of one record per entry, at a quarter of
+// the line traffic of two 8-B gathers of (ra, dec) from the caller's arrays.
+// A side that the filter reads in place gets only its (ra, dec) as one 16-B
+// record: the filter reads it once per entry, at a random place, and
+// computes the working record itself.
 __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
@@ -188,6 +182,10 @@ __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict_
           r.dec = d;
           src32[i] = r;
         }
+      } else if (radec32) {
+        // a side the filter reads in place (either form): its (ra, dec)
+        // only, from which the filter derives its unit vector or cell record
+        radec32[i] = make_double2(a, d);
       }
       if (halo && ok) {
         // the zone height is >= 2 r, so the padded Dec window reaches at

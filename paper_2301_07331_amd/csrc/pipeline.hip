@@ -31,7 +31,7 @@ void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n
   // the keygen also counts the first radix pass's digits of the tiles it alone fills
   const KeygenHist kh{sc.counts, sd.n_cap, sort_lo(g)};
   launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
-                l32 ? sd.cell32 : nullptr, l32 ? sd.srcrad : nullptr, l32 ? sd.src32 : nullptr, &kh,
+                l32 ? sd.cell32 : nullptr, sd.srcrad, l32 ? sd.src32 : nullptr, &kh,
                 iota_values(g, sd));
   mark(dev, sl.keygen, s);
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
@@ -237,14 +237,16 @@ void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n
   sd.r32 = (l32 && layout) ? c.take<CellRec32>(cap) : nullptr;
   const bool sorted = l32 && layout && sorted_radec;
   sd.radec = sorted ? c.take<double2>(cap) : nullptr;
-  sd.src64 = (l64 && n_src) ? c.take<Rec64>(n_src) : nullptr;
-  // FP32: a gathered side keeps cell records and (ra, dec) apart (the gather
-  // then reads from an array half the size), unless its (ra, dec) are
-  // gathered too; a side read in place keeps them together (one cache line
-  // per entry for both)
+  // A side read in place (either form) keeps only its (ra, dec), 16 B per
+  // source, from which the filter derives its working record. FP64: a
+  // gathered side's records are unit vector + index. FP32: a gathered side
+  // keeps cell records and (ra, dec) apart (the gather then reads from an
+  // array half the size), unless its (ra, dec) are gathered too (cell
+  // record and (ra, dec) together)
+  sd.src64 = (l64 && n_src && layout) ? c.take<Rec64>(n_src) : nullptr;
   sd.cell32 = (l32 && n_src && layout && !sorted) ? c.take<CellRec32>(n_src) : nullptr;
-  sd.srcrad = (l32 && n_src && layout && !sorted) ? c.take<double2>(n_src) : nullptr;
-  sd.src32 = (l32 && n_src && (!layout || sorted)) ? c.take<SrcRec32>(n_src) : nullptr;
+  sd.srcrad = (n_src && ((l32 && !sorted) || (l64 && !layout))) ? c.take<double2>(n_src) : nullptr;
+  sd.src32 = (l32 && n_src && sorted) ? c.take<SrcRec32>(n_src) : nullptr;
 }
 
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {

@@ -116,14 +116,6 @@ struct CellRec32 {
 constexpr float CELL_UNIT = 0x1p-34f;
 constexpr double CELL_SCALE = 0x1p34;
 
-// per-source FP32 record of a catalogue that the filter reads in place (32 B):
-// the cell record and the FP64 position, which share one cache line, so the
-// candidates of that catalogue carry their (ra, dec) at no extra read
-struct SrcRec32 {
-  CellRec32 c;
-  double ra, dec;
-};
-
 // the cell record of a unit vector (FP64 components in [-1, 1])
 __device__ inline CellRec32 encode_cell(double x, double y, double z) {
   CellRec32 r;

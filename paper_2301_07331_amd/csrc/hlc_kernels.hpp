@@ -21,11 +21,9 @@ struct SortScratch {
 // keys/vals for A (one entry per source, or one per source plus Dec-halo
 // copies appended after n when `halo` is set).
 // keys (and halo copies) of n sources (with iota_vals, the value of source i,
-// i itself, is left to the sort's first pass); with src64 (FP64 form), cell32 and
-// radec32 (FP32 form, a catalogue whose records are gathered) or src32 (FP32
-// form, a catalogue the filter reads in place) also each source's working
-// record in input order, for launch_gather64 / 32, the filter and the
-// certification
+// i itself, is left to the sort's first pass); with radec also each source's
+// (ra, dec) as one 16-B record in input order, the per-source record that
+// the layouts, the filter (a side read in place) and the certification read
 // The first radix pass's per-tile digit counts, filled by the keygen for
 // the tiles it alone writes (the sort's scratch counts of an entry capacity
 // cap, digit shift of the first pass).
@@ -36,15 +34,9 @@ struct KeygenHist {
 };
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
-                   Rec64* src64 = nullptr, CellRec32* cell32 = nullptr, double2* radec32 = nullptr,
-                   SrcRec32* src32 = nullptr, const KeygenHist* kh = nullptr, bool iota_vals = false);
+                   double2* radec = nullptr, const KeygenHist* kh = nullptr, bool iota_vals = false);
 // tiles of the first pass whose counts a keygen of n sources fills
 uint32_t keygen_hist_tiles(uint32_t n);
-void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s);
-void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* src, CellRec32* rec, hipStream_t s);
-// sorted cell records and sorted (ra, dec) (radec may be null) from 32-B per-source records
-void launch_gather32_radec(const uint32_t* vals, const DevCount& n, const SrcRec32* src, CellRec32* rec,
-                           double2* radec, hipStream_t s);
 
 size_t sort_counts_len(uint32_t n);
 size_t sort_digit_totals_len(uint32_t n);
@@ -82,13 +74,13 @@ void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, 
 void launch_zone_starts_index(const uint32_t* idx, int shift, uint32_t T, const DevCount& n, const Geom& g,
                               uint32_t* zstart, hipStream_t s, int32_t* zmarg = nullptr,
                               double* zdelta = nullptr);
+// sorted working records of a side: each entry's source position read from
+// il (the keygen's (ra, dec) records) when given, else from ra and dec
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     Rec64* rec, hipStream_t s);
+                     Rec64* rec, hipStream_t s, const double2* il = nullptr);
 // (and the sorted (ra, dec) when radec is not null)
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     CellRec32* rec, double2* radec, hipStream_t s);
-// radec[i] = (ra[i], dec[i]), i < n
-void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s);
+                     CellRec32* rec, double2* radec, hipStream_t s, const double2* il = nullptr);
 // lb[i] = number of B keys below keysA[i]; splits: merge_splits_len words of scratch
 size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap);
 void launch_merge_lb(const uint32_t* keysA, const DevCount& na, const uint32_t* keysB,
@@ -223,13 +215,10 @@ struct MatchArgs {
   // sorted index arrays (source index, halo bit included)
   const uint32_t* valsA;
   const uint32_t* valsB;
-  // A read in place (recA64 / recA32 unused): entry p's record is the
-  // keygen's per-source record of source valsA[p] (srcA64 / srcA32), or when
-  // that is null only the (ra, dec) in srcradA, from which the filter
-  // derives the unit vector or cell record
+  // A read in place (recA64 / recA32 unused): entry p's position is the
+  // keygen's (ra, dec) record of source valsA[p] (srcradA), from which the
+  // filter computes the unit vector or cell record
   int a_in_place;
-  const Rec64* srcA64;
-  const SrcRec32* srcA32;
   const uint32_t* keysA;
   const uint32_t* keysB;
   Geom geom;

@@ -229,16 +229,11 @@ struct Side {
   // sorted (ra, dec): FP32 form in the sorted certification layout (see
   // carve_side), and the paper-scheme emulation's pixel tests
   double2* radec = nullptr;
-  // per-source records written by the keygen in input order (nullptr: the
-  // layout computes the sorted records from the coordinates)
-  Rec64* src64 = nullptr;     // FP64 form, gathered side
-  CellRec32* cell32 = nullptr;  // FP32 form, gathered side: cell records
-  // (ra, dec) by original index: FP32 form, gathered side (for the
-  // certification); either form, a side read in place (its only record)
+  // (ra, dec) of each source, 16 B, written by the keygen in input order
+  // (nullptr: the layout reads the caller's coordinates): the sorted records
+  // of a gathered side are computed from it, the filter reads a side in
+  // place from it, and the certification reads B's positions from it
   double2* srcrad = nullptr;
-  // FP32 form: cell record + (ra, dec); a gathered side in the sorted
-  // certification layout (and the reusable partitions)
-  SrcRec32* src32 = nullptr;
   const double *ra = nullptr, *dec = nullptr;  // original coordinates (for the band list)
 };
 

@@ -492,13 +492,8 @@ __device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
   r.key = a.keysA[h.a_pos];
   const uint32_t idx = h.va;  // the entry's source index (halo bit included)
   if constexpr (F32) {
-    if (a.a_in_place && a.srcA32) {
-      const SrcRec32 s = a.srcA32[idx & IDX_MASK];
-      r.ca = s.c;
-      r.u0 = s.ra;
-      r.u1 = s.dec;
-    } else if (a.a_in_place) {
-      // (ra, dec) in place; the cell record as the keygen would write it
+    if (a.a_in_place) {
+      // (ra, dec) in place; the cell record as the layout would write it
       const double2 p = a.srcradA[idx & IDX_MASK];
       double x, y, z;
       unit_vector(p.x, p.y, x, y, z);
@@ -516,12 +511,12 @@ __device__ inline ARaw load_a(const MatchArgs& a, const ItemHead& h) {
       }
     }
   } else {
-    if (a.a_in_place && !a.srcA64) {
-      // (ra, dec) in place; the unit vector as the keygen would write it
+    if (a.a_in_place) {
+      // (ra, dec) in place; the unit vector as the layout would write it
       const double2 p = a.srcradA[idx & IDX_MASK];
       unit_vector(p.x, p.y, r.u0, r.u1, r.u2);
     } else {
-      const Rec64 s = a.a_in_place ? a.srcA64[idx & IDX_MASK] : a.recA64[h.a_pos];
+      const Rec64 s = a.recA64[h.a_pos];
       r.u0 = s.x;
       r.u1 = s.y;
       r.u2 = s.z;

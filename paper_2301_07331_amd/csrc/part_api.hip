@@ -68,8 +68,7 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     SortScratch sc;
     auto scratch = [&](Carve& c) {
       carve_sort(c, sc, std::max(cap, 1u));
-      p->side.src64 = c.take<Rec64>(std::max(nn, 1u));
-      p->side.src32 = c.take<SrcRec32>(std::max(nn, 1u));
+      p->side.srcrad = c.take<double2>(std::max(nn, 1u));
     };
     Carve ss{nullptr};
     scratch(ss);
@@ -86,8 +85,7 @@ int hlc_partition(const double* ra_deg, const double* dec_deg, int64_t n, double
     }
     launch_zero_counters(dev->cnt, s);
     st = partition(*dev, p->ra, p->dec, nn, p->g, true, true, true, sc, 1u, p->side, NO_SLOTS, s);
-    p->side.src64 = nullptr;
-    p->side.src32 = nullptr;
+    p->side.srcrad = nullptr;
     if (st == HLC_OK) {
       launch_zone_starts(p->side.keys, p->side.cnt, p->g, p->zstart, s);
       st = read_counters(*dev, s, false);

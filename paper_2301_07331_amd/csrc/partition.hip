@@ -87,24 +87,18 @@ constexpr uint32_t KG_THREADS = 512;
 constexpr uint32_t KG_TILE = KG_ITEMS * KG_THREADS;
 static_assert(KG_TILE == (uint32_t)RS_TILE, "a keygen block fills one radix tile");
 
-// Besides the keys, each source's working record is written in input order
-// (coalesced). A side that is gathered after its sort gets the FP64 record
-// (unit vector and index, 32 B), or for the FP32 form the 16-B cell record
-// and, in a second array, the FP64 (ra, dec) that certifies candidates; its
-// layout is then a single gather of one record per entry, at a quarter of
-// the line traffic of two 8-B gathers of (ra, dec) from the caller's arrays.
-// A side that the filter reads in place gets only its (ra, dec) as one 16-B
-// record: the filter reads it once per entry, at a random place, and
-// computes the working record itself.
+// Besides the keys, each source's (ra, dec) is written in input order as one
+// 16-B record (coalesced), when radec is given: the side's only per-source
+// record. A gathered side's layout then reads one random line per entry
+// (half the line traffic of two 8-B reads from the caller's arrays) and
+// computes the sorted working record from it; a side that the filter reads
+// in place is read once per entry there, the filter computing the record.
 __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict__ ra,
                                                 const double* __restrict__ dec, uint32_t n,
                                                 Geom g, int halo, uint32_t err_bit,
                                                 uint32_t* __restrict__ keys,
                                                 uint32_t* __restrict__ vals, Counters* cnt,
-                                                Rec64* __restrict__ src64,
-                                                CellRec32* __restrict__ cell32,
-                                                double2* __restrict__ radec32,
-                                                SrcRec32* __restrict__ src32, uint32_t* __restrict__ hist,
+                                                double2* __restrict__ radec, uint32_t* __restrict__ hist,
                                                 uint32_t hist_tiles, int hist_shift, uint32_t hist_full,
                                                 int iota_vals) {
   constexpr int NW = KG_THREADS / 64;
@@ -159,34 +153,7 @@ __global__ __launch_bounds__(KG_THREADS) void k_keygen(const double* __restrict_
       keys[i] = key;
       if (!iota_vals) vals[i] = i;  // (else the sort's first pass takes the position)
       if (count) atomicAdd(&s_h[(key >> hist_shift) & 0xffu], 1u);
-      if (src64 || cell32 || src32) {
-        double x, y, w;
-        unit_vector(a, d, x, y, w);
-        if (src64) {
-          Rec64 r;
-          r.x = x;
-          r.y = y;
-          r.z = w;
-          r.idx = i;
-          r.pad = 0u;
-          src64[i] = r;
-        }
-        if (cell32) {
-          cell32[i] = encode_cell(x, y, w);
-          radec32[i] = make_double2(a, d);
-        }
-        if (src32) {
-          SrcRec32 r;
-          r.c = encode_cell(x, y, w);
-          r.ra = a;
-          r.dec = d;
-          src32[i] = r;
-        }
-      } else if (radec32) {
-        // a side the filter reads in place (either form): its (ra, dec)
-        // only, from which the filter derives its unit vector or cell record
-        radec32[i] = make_double2(a, d);
-      }
+      if (radec) radec[i] = make_double2(a, d);
       if (halo && ok) {
         // the zone height is >= 2 r, so the padded Dec window reaches at
         // most one neighbouring zone
@@ -472,9 +439,12 @@ __global__ void k_zone_starts_index(const uint32_t* __restrict__ idx, int shift,
 // ---------------------------------------------------------------------------
 // working layouts
 // ---------------------------------------------------------------------------
+// FP64 record (unit vector + the entry's value) of each sorted entry, from
+// the caller's coordinates or from the keygen's interleaved (ra, dec) (il)
 __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
+                                                  const double2* __restrict__ il,
                                                   Rec64* __restrict__ rec) {
   // XCD-aware over the blocks the device-side count fills (the grid covers the
   // capacity): the sources a run of sorted entries reads land in one L2
@@ -484,8 +454,17 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
   if (p >= n) return;
   uint32_t v = vals[p];
   uint32_t i = v & IDX_MASK;
+  double a, d;
+  if (il) {
+    const double2 q = il[i];
+    a = q.x;
+    d = q.y;
+  } else {
+    a = ra[i];
+    d = dec[i];
+  }
   double x, y, z;
-  unit_vector(ra[i], dec[i], x, y, z);
+  unit_vector(a, d, x, y, z);
   Rec64 r;
   r.x = x;
   r.y = y;
@@ -496,63 +475,29 @@ __global__ __launch_bounds__(256) void k_layout64(const uint32_t* __restrict__ v
 }
 
 // FP32 cell record of the FP64 unit vector (and, with radec, the (ra, dec)),
-// sorted, from the caller's coordinates
+// sorted, from the caller's coordinates or from the keygen's interleaved
+// (ra, dec) records (il)
 __global__ __launch_bounds__(256) void k_layout32(const uint32_t* __restrict__ vals, DevCount nc,
                                                   const double* __restrict__ ra,
                                                   const double* __restrict__ dec,
+                                                  const double2* __restrict__ il,
                                                   CellRec32* __restrict__ rec, double2* __restrict__ radec) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc.get()) return;
   uint32_t i = vals[p] & IDX_MASK;
-  const double a = ra[i], d = dec[i];
+  double a, d;
+  if (il) {
+    const double2 q = il[i];
+    a = q.x;
+    d = q.y;
+  } else {
+    a = ra[i];
+    d = dec[i];
+  }
   double x, y, z;
   unit_vector(a, d, x, y, z);
   rec[p] = encode_cell(x, y, z);
   if (radec) radec[p] = make_double2(a, d);
-}
-
-// (ra, dec) of each source interleaved, in input order
-__global__ __launch_bounds__(256) void k_interleave(const double* __restrict__ ra, const double* __restrict__ dec,
-                                                    uint32_t n, double2* __restrict__ radec) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) radec[i] = make_double2(ra[i], dec[i]);
-}
-
-// Sorted working records from the per-source records of the keygen.
-__global__ __launch_bounds__(256) void k_gather64(const uint32_t* __restrict__ vals, DevCount nc,
-                                                  const Rec64* __restrict__ src,
-                                                  Rec64* __restrict__ rec) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nc.get()) return;
-  const uint32_t v = vals[p];
-  Rec64 r = src[v & IDX_MASK];
-  r.idx = v;
-  rec[p] = r;
-}
-
-// Sorted FP32 cell records from the keygen's (16 B each: the gathered array
-// is half the size of the FP64 form's, so more of it stays in the device's
-// last-level cache between the reads of one 128-B line's eight records).
-__global__ __launch_bounds__(256) void k_gather32(const uint32_t* __restrict__ vals, DevCount nc,
-                                                  const CellRec32* __restrict__ src,
-                                                  CellRec32* __restrict__ rec) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nc.get()) return;
-  rec[p] = src[vals[p] & IDX_MASK];
-}
-
-// Sorted cell records and sorted (ra, dec) from the keygen's 32-B
-// per-source records (one random line per entry for both), for a
-// certification that reads a candidate's B (ra, dec) at its sorted position,
-// where the other candidates of its group read too.
-__global__ __launch_bounds__(256) void k_gather32_radec(const uint32_t* __restrict__ vals, DevCount nc,
-                                                        const SrcRec32* __restrict__ src,
-                                                        CellRec32* __restrict__ rec, double2* __restrict__ radec) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nc.get()) return;
-  const SrcRec32& r = src[vals[p] & IDX_MASK];
-  rec[p] = r.c;
-  if (radec) radec[p] = make_double2(r.ra, r.dec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,8 +1087,7 @@ void launch_zero_counters(Counters* c, hipStream_t s) { k_zero_counters<<<1, 64,
 
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
-                   Rec64* src64, CellRec32* cell32, double2* radec32, SrcRec32* src32, const KeygenHist* kh,
-                   bool iota_vals) {
+                   double2* radec, const KeygenHist* kh, bool iota_vals) {
   if (n == 0) return;
   uint32_t* hist = nullptr;
   uint32_t tiles = 0, full = 0;
@@ -1156,25 +1100,8 @@ void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& 
     hist = full ? kh->counts : nullptr;
   }
   k_keygen<<<std::max<uint32_t>(1, cdiv(n, KG_TILE)), KG_THREADS, 0, s>>>(
-      ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt, src64, cell32, radec32, src32, hist, tiles, shift,
+      ra, dec, n, g, halo ? 1 : 0, err_bit, keys, vals, cnt, radec, hist, tiles, shift,
       full, iota_vals ? 1 : 0);
-}
-
-void launch_gather64(const uint32_t* vals, const DevCount& n, const Rec64* src, Rec64* rec, hipStream_t s) {
-  if (n.cap == 0) return;
-  k_gather64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
-}
-
-void launch_gather32(const uint32_t* vals, const DevCount& n, const CellRec32* src, CellRec32* rec,
-                     hipStream_t s) {
-  if (n.cap == 0) return;
-  k_gather32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec);
-}
-
-void launch_gather32_radec(const uint32_t* vals, const DevCount& n, const SrcRec32* src, CellRec32* rec,
-                           double2* radec, hipStream_t s) {
-  if (n.cap == 0) return;
-  k_gather32_radec<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, src, rec, radec);
 }
 
 size_t sort_counts_len(uint32_t n) { return (size_t)RS_BINS * std::max<uint32_t>(1, cdiv(n, RS_TILE)); }
@@ -1264,20 +1191,15 @@ void launch_zone_starts(const uint32_t* keys, const DevCount& n, const Geom& g, 
 }
 
 void launch_layout64(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     Rec64* rec, hipStream_t s) {
+                     Rec64* rec, hipStream_t s, const double2* il) {
   if (n.cap == 0) return;
-  k_layout64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec);
+  k_layout64<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, il, rec);
 }
 
 void launch_layout32(const uint32_t* vals, const DevCount& n, const double* ra, const double* dec,
-                     CellRec32* rec, double2* radec, hipStream_t s) {
+                     CellRec32* rec, double2* radec, hipStream_t s, const double2* il) {
   if (n.cap == 0) return;
-  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, rec, radec);
-}
-
-void launch_interleave(const double* ra, const double* dec, uint32_t n, double2* radec, hipStream_t s) {
-  if (n == 0) return;
-  k_interleave<<<cdiv(n, 256), 256, 0, s>>>(ra, dec, n, radec);
+  k_layout32<<<cdiv(n.cap, 256), 256, 0, s>>>(vals, n, ra, dec, il, rec, radec);
 }
 
 size_t merge_splits_len(uint64_t na_cap, uint64_t nb_cap) { return (size_t)cdiv(na_cap + nb_cap, MP_TILE) + 1; }

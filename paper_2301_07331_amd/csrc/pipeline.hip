@@ -30,9 +30,7 @@ void partition_keys(Device& dev, const double* ra, const double* dec, uint32_t n
   sd.n_cap = halo ? 2 * n : n;
   // the keygen also counts the first radix pass's digits of the tiles it alone fills
   const KeygenHist kh{sc.counts, sd.n_cap, sort_lo(g)};
-  launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, l64 ? sd.src64 : nullptr,
-                l32 ? sd.cell32 : nullptr, sd.srcrad, l32 ? sd.src32 : nullptr, &kh,
-                iota_values(g, sd));
+  launch_keygen(ra, dec, n, g, halo, err_bit, kk, vv, dev.cnt, s, sd.srcrad, &kh, iota_values(g, sd));
   mark(dev, sl.keygen, s);
   sd.cnt = halo ? DevCount{n, 2 * n, &dev.cnt->n_halo} : DevCount{n, n, nullptr};
 }
@@ -46,20 +44,10 @@ int partition_sort(Device& dev, const Geom& g, bool l64, bool l32, const SortScr
              iota_values(g, sd) ? sd.n_src : 0u);
   mark(dev, sl.sort, s);
   if (sorted_ev) HLC_TRY(hipEventRecord(sorted_ev, s));
-  if (l64 && sd.r64) {
-    if (sd.src64) launch_gather64(sd.vals, sd.cnt, sd.src64, sd.r64, s);
-    else launch_layout64(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r64, s);
-  }
-  if (l32 && sd.r32) {
-    if (sd.cell32) {
-      launch_gather32(sd.vals, sd.cnt, sd.cell32, sd.r32, s);
-    } else if (sd.src32) {
-      launch_gather32_radec(sd.vals, sd.cnt, sd.src32, sd.r32, sd.radec, s);
-    } else {
-      launch_layout32(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r32, sd.radec, s);
-      if (sd.srcrad) launch_interleave(sd.ra, sd.dec, sd.n_src, sd.srcrad, s);
-    }
-  }
+  // the sorted records from the keygen's (ra, dec) records when it wrote
+  // them (one random line per entry), else from the caller's arrays
+  if (l64 && sd.r64) launch_layout64(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r64, s, sd.srcrad);
+  if (l32 && sd.r32) launch_layout32(sd.vals, sd.cnt, sd.ra, sd.dec, sd.r32, sd.radec, s, sd.srcrad);
   mark(dev, sl.layout, s);
   return HLC_OK;
 }
@@ -190,8 +178,6 @@ void match(Device& dev, const Side& A, const Side& B, const Geom& g, double r_ar
   ma.valsB = B.vals;
   if (!(fp32 ? (const void*)A.r32 : (const void*)A.r64)) {
     ma.a_in_place = 1;
-    ma.srcA64 = A.src64;
-    ma.srcA32 = A.src32;
   }
   ma.geom = g;
   ma.H_lo = th.H_lo;
@@ -237,16 +223,11 @@ void carve_side(Carve& c, Side& sd, uint32_t cap, bool l64, bool l32, uint32_t n
   sd.r32 = (l32 && layout) ? c.take<CellRec32>(cap) : nullptr;
   const bool sorted = l32 && layout && sorted_radec;
   sd.radec = sorted ? c.take<double2>(cap) : nullptr;
-  // A side read in place (either form) keeps only its (ra, dec), 16 B per
-  // source, from which the filter derives its working record. FP64: a
-  // gathered side's records are unit vector + index. FP32: a gathered side
-  // keeps cell records and (ra, dec) apart (the gather then reads from an
-  // array half the size), unless its (ra, dec) are gathered too (cell
-  // record and (ra, dec) together)
-  sd.src64 = (l64 && n_src && layout) ? c.take<Rec64>(n_src) : nullptr;
-  sd.cell32 = (l32 && n_src && layout && !sorted) ? c.take<CellRec32>(n_src) : nullptr;
-  sd.srcrad = (n_src && ((l32 && !sorted) || (l64 && !layout))) ? c.take<double2>(n_src) : nullptr;
-  sd.src32 = (l32 && n_src && sorted) ? c.take<SrcRec32>(n_src) : nullptr;
+  // the one per-source record: (ra, dec), 16 B, written by the keygen; the
+  // layout computes a gathered side's sorted records from it, the filter a
+  // side read in place, and the certification reads it for B's positions
+  // (unless they are sorted too)
+  sd.srcrad = ((l64 || l32) && n_src) ? c.take<double2>(n_src) : nullptr;
 }
 
 void carve_sort(Carve& c, SortScratch& sc, uint32_t nmax) {

@@ -28,6 +28,12 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 32;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 8192 keys per tile
 constexpr int RS_BINS = 256;
+// the scatter: 512 threads, 16 keys each, per 8,192-key tile (eight waves,
+// each ranking a contiguous eighth of the tile)
+constexpr int SC_THREADS = 512;
+constexpr int SC_ITEMS = 16;
+constexpr int SC_WAVES = SC_THREADS / 64;
+static_assert(SC_THREADS * SC_ITEMS == RS_TILE, "a scatter block ranks one radix tile");
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
@@ -246,17 +252,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_scan_digits(uint32_t* __restrict
 // that a block's loads do not wait behind its own ranking. A tile is ranked
 // in LDS (per-wave digit counts, 8 ballots per item for the lanes sharing a
 // digit) and leaves in runs of consecutive positions.
-__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
+__global__ __launch_bounds__(SC_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, DevCount nc, int shift,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ totals, uint32_t ntiles, uint32_t iota) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[RS_TILE];
-  __shared__ uint32_t s_wh[4][RS_BINS];
+  __shared__ uint32_t s_wh[SC_WAVES][RS_BINS];
   __shared__ uint32_t s_start[RS_BINS];
   __shared__ uint32_t s_goff[RS_BINS];
   __shared__ uint32_t s_dbase[RS_BINS];
-  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_w[SC_WAVES];
   const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t n = nc.get();
   const uint32_t nt = (uint32_t)(((uint64_t)n + RS_TILE - 1) / RS_TILE);
@@ -265,66 +271,79 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   {
     // digit d's first position before any tile's share: the same for every tile
     uint32_t all;
-    s_dbase[t] = block_exclusive_scan(totals[t], &all, s_w);
+    const uint32_t st = block_exclusive_scan<SC_WAVES>(t < RS_BINS ? totals[t] : 0u, &all, s_w);
+    if (t < RS_BINS) s_dbase[t] = st;
   }
-  auto load = [&](uint32_t tl, uint32_t (&k)[RS_ITEMS], uint32_t (&v)[RS_ITEMS], uint32_t& off) {
-    const uint32_t e0 = tl * RS_TILE + w * (RS_TILE / 4) + lane;
-    off = offsets[t * ntiles + tl];
+  auto load = [&](uint32_t tl, uint32_t (&k)[SC_ITEMS], uint32_t (&v)[SC_ITEMS], uint32_t& off) {
+    const uint32_t e0 = tl * RS_TILE + w * (RS_TILE / SC_WAVES) + lane;
+    off = t < RS_BINS ? offsets[t * ntiles + tl] : 0u;
     // (entries below iota carry their own position as value: not loaded)
     if (tl * RS_TILE + RS_TILE <= min(n, iota)) {
 #pragma unroll
-      for (int j = 0; j < RS_ITEMS; ++j) {
+      for (int j = 0; j < SC_ITEMS; ++j) {
         k[j] = keys_in[e0 + j * 64];
         v[j] = e0 + j * 64;
       }
     } else if (tl * RS_TILE + RS_TILE <= n) {
 #pragma unroll
-      for (int j = 0; j < RS_ITEMS; ++j) {
+      for (int j = 0; j < SC_ITEMS; ++j) {
         const uint32_t e = e0 + j * 64;
         k[j] = keys_in[e];
         v[j] = e < iota ? e : vals_in[e];
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < RS_ITEMS; ++j) {
+      for (int j = 0; j < SC_ITEMS; ++j) {
         const uint32_t e = e0 + j * 64;
         k[j] = e < n ? keys_in[e] : 0u;
         v[j] = e < n ? (e < iota ? e : vals_in[e]) : 0u;
       }
     }
   };
-  uint32_t key[RS_ITEMS], val[RS_ITEMS], off;
+  uint32_t key[SC_ITEMS], val[SC_ITEMS], off;
   load(tile, key, val, off);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   while (true) {
     const uint32_t base = tile * RS_TILE;
     const uint32_t tile_n = min((uint32_t)RS_TILE, n - base);
     const uint32_t next = tile + gridDim.x;
-    for (uint32_t k = t; k < 4 * RS_BINS; k += RS_THREADS) (&s_wh[0][0])[k] = 0u;
-    s_goff[t] = s_dbase[t] + off;
+    for (uint32_t k = t; k < SC_WAVES * RS_BINS; k += SC_THREADS) (&s_wh[0][0])[k] = 0u;
+    if (t < RS_BINS) s_goff[t] = s_dbase[t] + off;
     __syncthreads();
-    const uint32_t e0 = base + w * (RS_TILE / 4) + lane;
+    const uint32_t e0 = base + w * (RS_TILE / SC_WAVES) + lane;
 #pragma unroll
-    for (int j = 0; j < RS_ITEMS; ++j)
+    for (int j = 0; j < SC_ITEMS; ++j)
       if (e0 + j * 64 < n) atomicAdd(&s_wh[w][(key[j] >> shift) & 0xffu], 1u);
     __syncthreads();
     {
+      // digit d's start in the tile, then each wave's start within it
       const uint32_t d = t;
-      uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
+      uint32_t c[SC_WAVES] = {}, sum = 0u;
+      if (d < RS_BINS) {
+#pragma unroll
+        for (int k = 0; k < SC_WAVES; ++k) {
+          c[k] = s_wh[k][d];
+          sum += c[k];
+        }
+      }
       uint32_t tot;
-      uint32_t st = block_exclusive_scan(c0 + c1 + c2 + c3, &tot, s_w);
-      s_start[d] = st;
-      s_wh[0][d] = st;
-      s_wh[1][d] = st + c0;
-      s_wh[2][d] = st + c0 + c1;
-      s_wh[3][d] = st + c0 + c1 + c2;
+      const uint32_t st = block_exclusive_scan<SC_WAVES>(sum, &tot, s_w);
+      if (d < RS_BINS) {
+        s_start[d] = st;
+        uint32_t run = st;
+#pragma unroll
+        for (int k = 0; k < SC_WAVES; ++k) {
+          s_wh[k][d] = run;
+          run += c[k];
+        }
+      }
     }
     __syncthreads();
     // the next tile in flight from here on
-    uint32_t nkey[RS_ITEMS], nval[RS_ITEMS], noff = 0u;
+    uint32_t nkey[SC_ITEMS], nval[SC_ITEMS], noff = 0u;
     if (next < nt) load(next, nkey, nval, noff);
 #pragma unroll
-    for (int j = 0; j < RS_ITEMS; ++j) {
+    for (int j = 0; j < SC_ITEMS; ++j) {
       const uint32_t e = e0 + j * 64;
       const bool valid = e < n;
       const uint32_t d = (key[j] >> shift) & 0xffu;
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
       }
     }
     __syncthreads();
-    for (uint32_t i = t; i < tile_n; i += RS_THREADS) {
+    for (uint32_t i = t; i < tile_n; i += SC_THREADS) {
       const uint32_t k = s_k[i];
       const uint32_t d = (k >> shift) & 0xffu;
       const uint32_t gpos = s_goff[d] + (i - s_start[d]);
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     }
     if (next >= nt) break;
 #pragma unroll
-    for (int j = 0; j < RS_ITEMS; ++j) {
+    for (int j = 0; j < SC_ITEMS; ++j) {
       key[j] = nkey[j];
       val[j] = nval[j];
     }
@@ -1142,7 +1161,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, const DevCount& cnt, int key_bit
       const uint32_t h0 = p == 0 ? std::min(hist_done, ntiles) : 0u;
       if (h0 < ntiles) k_radix_hist<<<ntiles - h0, RS_THREADS, 0, s>>>(kin, cnt, shift, sc.counts, ntiles, h0);
       k_scan_digits<<<RS_BINS, RS_THREADS, 0, s>>>(sc.counts, ntiles, sc.digit_totals);
-      k_radix_scatter<<<std::min<uint32_t>(ntiles, scatter_blocks()), RS_THREADS, 0, s>>>(
+      k_radix_scatter<<<std::min<uint32_t>(ntiles, scatter_blocks()), SC_THREADS, 0, s>>>(
           kin, vin, kout, vout, cnt, shift, sc.counts, sc.digit_totals, ntiles, p == 0 ? iota : 0u);
       std::swap(kin, kout);
       std::swap(vin, vout);

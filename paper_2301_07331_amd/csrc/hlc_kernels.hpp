@@ -18,12 +18,6 @@ struct SortScratch {
   uint32_t* digit_totals; // per-digit totals of one pass
 };
 
-// keys/vals for A (one entry per source, or one per source plus Dec-halo
-// copies appended after n when `halo` is set).
-// keys (and halo copies) of n sources (with iota_vals, the value of source i,
-// i itself, is left to the sort's first pass); with radec also each source's
-// (ra, dec) as one 16-B record in input order, the per-source record that
-// the layouts, the filter (a side read in place) and the certification read
 // The first radix pass's per-tile digit counts, filled by the keygen for
 // the tiles it alone writes (the sort's scratch counts of an entry capacity
 // cap, digit shift of the first pass).
@@ -32,6 +26,12 @@ struct KeygenHist {
   uint32_t cap;
   int shift;
 };
+// keys/vals of n sources: one entry per source, plus the Dec-halo copies
+// appended after n when `halo` is set (with iota_vals, the value of source
+// i, i itself, is left to the sort's first pass); with radec also each
+// source's (ra, dec) as one 16-B record in input order, the per-source
+// record that the layouts, the filter (a side read in place) and the
+// certification read
 void launch_keygen(const double* ra, const double* dec, uint32_t n, const Geom& g, bool halo,
                    uint32_t err_bit, uint32_t* keys, uint32_t* vals, Counters* cnt, hipStream_t s,
                    double2* radec = nullptr, const KeygenHist* kh = nullptr, bool iota_vals = false);

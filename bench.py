@@ -177,6 +177,31 @@ def pmc_summary(ktrace_dir, pmc_dirs):
     return "\n".join(out)
 
 
+def call_timeline(ktrace_dir, call):
+    """The kernels of one cross-match call, in start order, from a rocprofv3
+    --kernel-trace -f csv folder: queue, start and end (us from the call's
+    first kernel, the footprint sample) and duration. `call` counts the
+    calls of the traced run from 0. Markdown."""
+    import csv
+    rows = []
+    for f in _csvs(ktrace_dir, "kernel_trace.csv"):
+        for r in csv.DictReader(open(f)):
+            if "hlc" in r["Kernel_Name"]:
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", ""),
+                             short_kernel(r["Kernel_Name"])))
+    rows.sort()
+    starts = [i for i, r in enumerate(rows) if r[3] == "k_extent_sample"]
+    if call >= len(starts):
+        raise SystemExit(f"the trace holds {len(starts)} calls")
+    i0 = starts[call]
+    i1 = starts[call + 1] if call + 1 < len(starts) else len(rows)
+    t0 = rows[i0][0]
+    out = ["| queue | start us | end us | us | kernel |", "|---|---|---|---|---|"]
+    for (a, b, q, k) in rows[i0:i1]:
+        out.append(f"| {q} | {(a - t0) / 1e3:.1f} | {(b - t0) / 1e3:.1f} | {(b - a) / 1e3:.1f} | {k} |")
+    return "\n".join(out)
+
+
 def warm_up(call, calls, seconds=0.3):
     """Untimed calls: at least `calls` of them and at least `seconds` of them,
     so the GPU has left its idle clocks before the timed region."""
@@ -221,6 +246,9 @@ def parse():
     p.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                    help="print a per-kernel counter table from a rocprofv3 --kernel-trace --stats folder "
                         "followed by one or more --pmc folders, and exit")
+    p.add_argument("--timeline", nargs=2, metavar=("KTRACE_DIR", "CALL"),
+                   help="print the kernels of one call (numbered from 0) from a rocprofv3 --kernel-trace -f csv "
+                        "folder, and exit")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="print the filter kernel's HBM traffic from two rocprofv3 --pmc output folders and exit")
     return p.parse_args()
@@ -421,6 +449,9 @@ def main():
     args = parse()
     if args.pmc_summary:
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1:]))
+        return
+    if args.timeline:
+        print(call_timeline(args.timeline[0], int(args.timeline[1])))
         return
     if args.traffic_from:
         print(json.dumps(traffic_from_pmc(*args.traffic_from)))

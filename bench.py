@@ -177,11 +177,14 @@ def pmc_summary(ktrace_dir, pmc_dirs):
     return "\n".join(out)
 
 
-def call_timeline(ktrace_dir, call):
-    """The kernels of one cross-match call, in start order, from a rocprofv3
+def call_timeline(ktrace_dir, call, first="k_extent_sample", with_kernel=None):
+    """The kernels of one call, in start order, from a rocprofv3
     --kernel-trace -f csv folder: queue, start and end (us from the call's
-    first kernel, the footprint sample) and duration. `call` counts the
-    calls of the traced run from 0. Markdown."""
+    first kernel) and duration. A call starts at each launch of `first` (the
+    footprint sample of a single call; k_zero_u64 for the batched form);
+    with `with_kernel` only the calls that launch a kernel of that name
+    count. `call` indexes those calls from 0 (negative: from the last).
+    Markdown."""
     import csv
     rows = []
     for f in _csvs(ktrace_dir, "kernel_trace.csv"):
@@ -190,14 +193,16 @@ def call_timeline(ktrace_dir, call):
                 rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", ""),
                              short_kernel(r["Kernel_Name"])))
     rows.sort()
-    starts = [i for i, r in enumerate(rows) if r[3] == "k_extent_sample"]
-    if call >= len(starts):
-        raise SystemExit(f"the trace holds {len(starts)} calls")
-    i0 = starts[call]
-    i1 = starts[call + 1] if call + 1 < len(starts) else len(rows)
-    t0 = rows[i0][0]
+    starts = [i for i, r in enumerate(rows) if r[3] == first] + [len(rows)]
+    calls = [rows[a:b] for a, b in zip(starts[:-1], starts[1:])]
+    if with_kernel:
+        calls = [c for c in calls if any(r[3] == with_kernel for r in c)]
+    if not -len(calls) <= call < len(calls):
+        raise SystemExit(f"the trace holds {len(calls)} such calls")
+    sel = calls[call]
+    t0 = sel[0][0]
     out = ["| queue | start us | end us | us | kernel |", "|---|---|---|---|---|"]
-    for (a, b, q, k) in rows[i0:i1]:
+    for (a, b, q, k) in sel:
         out.append(f"| {q} | {(a - t0) / 1e3:.1f} | {(b - t0) / 1e3:.1f} | {(b - a) / 1e3:.1f} | {k} |")
     return "\n".join(out)
 
@@ -246,9 +251,11 @@ def parse():
     p.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                    help="print a per-kernel counter table from a rocprofv3 --kernel-trace --stats folder "
                         "followed by one or more --pmc folders, and exit")
-    p.add_argument("--timeline", nargs=2, metavar=("KTRACE_DIR", "CALL"),
-                   help="print the kernels of one call (numbered from 0) from a rocprofv3 --kernel-trace -f csv "
-                        "folder, and exit")
+    p.add_argument("--timeline", nargs="+", metavar="ARG",
+                   help="KTRACE_DIR CALL [FIRST_KERNEL [WITH_KERNEL]]: print the kernels of one call (numbered "
+                        "from 0, negative from the last; calls start at FIRST_KERNEL, default k_extent_sample, and "
+                        "count only if they launch WITH_KERNEL) from a rocprofv3 --kernel-trace -f csv folder, "
+                        "and exit")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="print the filter kernel's HBM traffic from two rocprofv3 --pmc output folders and exit")
     return p.parse_args()
@@ -451,7 +458,7 @@ def main():
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1:]))
         return
     if args.timeline:
-        print(call_timeline(args.timeline[0], int(args.timeline[1])))
+        print(call_timeline(args.timeline[0], int(args.timeline[1]), *args.timeline[2:4]))
         return
     if args.traffic_from:
         print(json.dumps(traffic_from_pmc(*args.traffic_from)))
